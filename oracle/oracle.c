@@ -1,0 +1,351 @@
+/*
+ * oracle.c -- plain, slow CPU reference for the fused Poisson relaxation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * with the HIP library.
+ *
+ * What it computes (ProtoX paper, Section IV "2D Poisson equation" and
+ * "Algorithm"):
+ *   - the 2D Poisson problem  Laplace(phi) = rho  on the unit square (Eq. 2),
+ *   - discretised with the 5-point stencil S, a special case of the generic
+ *     constant-coefficient stencil  S(x)_i = sum_j alpha_j x_{i+j}  (Eq. 1),
+ *     with taps [0,1,0; 1,-4,1; 0,1,0] (the filter t of the OL expression),
+ *   - one Jacobi step  phi^n = phi^{n-1} + lambda (S(phi^{n-1})/h^2 - rho)
+ *     (Eq. 3), written in the OL form Jacobi = (1, w, -lambda) (x) I with
+ *     w = lambda/h^2 acting on [phi; S phi; rho],
+ *   - the max-norm  || (0, 1/h^2, -1) (x) I [phi; S phi; rho] ||_inf  of the
+ *     OL expression for the norm, i.e. the residual of the iterate that the
+ *     sweep READS (the OL places Jacobi and the norm side by side on the same
+ *     input).
+ *
+ * The sweep is evaluated exactly as the three-step algorithm states it, one
+ * full pass per step and a separate temporary for S(phi): (1) apply the
+ * Laplacian, (2) the Jacobi update into a separate output array, (3) the
+ * max-norm.  No fusion, tiling or reordering.
+ *
+ * Readings (the paper is silent or ambiguous on these):
+ *   - association: the stencil sum is ((((N - 4C) + W) + E) + S) and the
+ *     update is ((phi + w*s) - lambda*rho), the order the generated fused
+ *     code in the paper's CPU figure uses; no fused multiply-add (compile
+ *     with -ffp-contract=off);
+ *   - boundary: homogeneous Dirichlet at the cell faces of a cell-centred
+ *     grid (h = 1/n), realised as odd reflection: ghost = -(adjacent
+ *     interior), refreshed before every sweep; corner ghosts = +(diagonal
+ *     interior) (reflection in both directions).  The alternative
+ *     GHOST_FIXED mode reads the ghost ring as given and never changes it
+ *     (the literal behaviour of the paper's generated code, which reads
+ *     ghost cells and never writes them);
+ *   - residual vector:  r = rho - (1/h^2) s.  The paper's norm takes
+ *     |(1/h^2) s - rho|, which is the same number bit for bit;
+ *   - the max is NaN-propagating (a NaN residual makes the norm NaN);
+ *   - also reported: sum of r^2 (for the L2 norm), accumulated in FP64 in
+ *     plain row-major order.
+ *
+ * Layout: phi is (n+2) rows x ld doubles, row-major, interior at rows and
+ * columns 1..n, ghost ring around it.  rho (called f here) is n rows x ld_f,
+ * compact, f[(i-1)*ld_f + (j-1)] belongs to phi cell (i, j).
+ *
+ * Precision variants:
+ *   ox_*_f64   FP64 storage and arithmetic (the oracle proper),
+ *   ox_*_f32   FP32 storage and arithmetic, constants rounded once from FP64,
+ *   ox_*_bf16  bfloat16 storage (round-to-nearest-even on every store),
+ *              FP32 arithmetic.
+ * All three follow the same steps; only the storage type changes.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+enum { OX_BC_DIRICHLET0 = 0, OX_BC_GHOST_FIXED = 1 };
+enum { OX_RES_NONE = 0, OX_RES_LAGGED = 1, OX_RES_FINAL = 2 };
+
+/* ------------------------------------------------------------------ */
+/* bfloat16 storage: top 16 bits of an IEEE binary32, rounded to nearest,
+ * ties to even; NaN stays NaN (quiet).                                  */
+/* ------------------------------------------------------------------ */
+uint16_t ox_f32_to_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu) != 0)
+        return (uint16_t)((u >> 16) | 0x0040u); /* quiet NaN */
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+float ox_bf16_to_f32(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
+}
+
+/* NaN-propagating maximum of non-negative magnitudes. */
+static double nanmax_d(double a, double b)
+{
+    if (isnan(a)) return a;
+    if (isnan(b)) return b;
+    return (b > a) ? b : a;
+}
+
+/* Visiting order of the nine taps of a 3x3 stencil, as (row, col) offsets.
+ * For the 5-point Laplacian this is exactly the order N, C, W, E, S of the
+ * paper's generated code; zero taps are skipped entirely. */
+static const int TAP_ORDER[9][2] = {
+    {-1, 0}, {0, 0}, {0, -1}, {0, 1}, {1, 0},
+    {-1, -1}, {-1, 1}, {1, -1}, {1, 1}};
+
+/* ================================================================== */
+/* Type-generic body, instantiated for (storage, arithmetic) pairs.     */
+/* LOAD(x) turns a stored value into the arithmetic type, STORE(v)      */
+/* rounds an arithmetic value into storage.                            */
+/* ================================================================== */
+#define OX_DEFINE(SUF, ST, AT, LOAD, STORE)                                          \
+                                                                                     \
+/* Step 0: a working copy of phi with the ghost ring refreshed per the BC. */       \
+static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, int bc)                 \
+{                                                                                    \
+    int m = n + 2;                                                                   \
+    AT *w = (AT *)malloc(sizeof(AT) * (size_t)m * m);                                \
+    for (int i = 0; i < m; ++i)                                                      \
+        for (int j = 0; j < m; ++j)                                                  \
+            w[(size_t)i * m + j] = LOAD(phi[(size_t)i * ld + j]);                    \
+    if (bc == OX_BC_DIRICHLET0) {                                                    \
+        for (int k = 1; k <= n; ++k) {                                               \
+            w[(size_t)0 * m + k] = -w[(size_t)1 * m + k];                            \
+            w[(size_t)(n + 1) * m + k] = -w[(size_t)n * m + k];                      \
+            w[(size_t)k * m + 0] = -w[(size_t)k * m + 1];                            \
+            w[(size_t)k * m + (n + 1)] = -w[(size_t)k * m + n];                      \
+        }                                                                            \
+        w[0] = w[(size_t)1 * m + 1];                                                 \
+        w[n + 1] = w[(size_t)1 * m + n];                                             \
+        w[(size_t)(n + 1) * m + 0] = w[(size_t)n * m + 1];                           \
+        w[(size_t)(n + 1) * m + n + 1] = w[(size_t)n * m + n];                       \
+    }                                                                                \
+    return w;                                                                        \
+}                                                                                    \
+                                                                                     \
+/* Step 1 (Eq. 1): temp(i,j) = sum over nonzero taps of tap * phi(i+a, j+b), in the  \
+ * fixed visiting order, for the n x n interior.  temp is n x n, compact. */         \
+static void stencil_pass_##SUF(const AT *w, int n, const double taps[9], AT *temp)   \
+{                                                                                    \
+    int m = n + 2;                                                                   \
+    AT t[9];                                                                         \
+    for (int k = 0; k < 9; ++k) t[k] = (AT)taps[k];                                  \
+    for (int i = 1; i <= n; ++i)                                                     \
+        for (int j = 1; j <= n; ++j) {                                               \
+            AT acc = 0;                                                              \
+            int first = 1;                                                           \
+            for (int k = 0; k < 9; ++k) {                                            \
+                int a = TAP_ORDER[k][0], b = TAP_ORDER[k][1];                        \
+                AT tap = t[(a + 1) * 3 + (b + 1)];                                   \
+                if (tap == 0) continue;                                              \
+                AT term = tap * w[(size_t)(i + a) * m + (j + b)];                    \
+                if (first) { acc = term; first = 0; }                                \
+                else acc = acc + term;                                               \
+            }                                                                        \
+            temp[(size_t)(i - 1) * n + (j - 1)] = acc;                               \
+        }                                                                            \
+}                                                                                    \
+                                                                                     \
+/* Step 3 (OL max-norm): r = f - c*s over the interior; norms[0] = max|r| (NaN      \
+ * propagating), norms[1] = sum r^2 in FP64, row-major order.  r_out optional. */    \
+static void norm_pass_##SUF(const AT *temp, int n, const ST *f, int ld_f, AT c,      \
+                            ST *r_out, int ld_r, double *norms)                      \
+{                                                                                    \
+    double mx = 0.0, sq = 0.0;                                                       \
+    for (int i = 0; i < n; ++i)                                                      \
+        for (int j = 0; j < n; ++j) {                                                \
+            AT r = LOAD(f[(size_t)i * ld_f + j]) - c * temp[(size_t)i * n + j];      \
+            if (r_out) r_out[(size_t)i * ld_r + j] = STORE(r);                       \
+            double rd = (double)r;                                                   \
+            mx = nanmax_d(mx, fabs(rd));                                             \
+            sq += rd * rd;                                                           \
+        }                                                                            \
+    if (norms) { norms[0] = mx; norms[1] = sq; }                                     \
+}                                                                                    \
+                                                                                     \
+/* Output ghost ring of a freshly written phi_out: odd reflection of the new       \
+ * interior (DIRICHLET0), or the input's ghosts unchanged (GHOST_FIXED).  The      \
+ * four corner cells are left untouched. */                                          \
+static void write_out_ghosts_##SUF(const ST *in, ST *out, int n, int ld, int bc)     \
+{                                                                                    \
+    for (int k = 1; k <= n; ++k) {                                                   \
+        if (bc == OX_BC_DIRICHLET0) {                                                \
+            out[(size_t)0 * ld + k] = STORE(-LOAD(out[(size_t)1 * ld + k]));         \
+            out[(size_t)(n + 1) * ld + k] = STORE(-LOAD(out[(size_t)n * ld + k]));   \
+            out[(size_t)k * ld + 0] = STORE(-LOAD(out[(size_t)k * ld + 1]));         \
+            out[(size_t)k * ld + n + 1] = STORE(-LOAD(out[(size_t)k * ld + n]));     \
+        } else {                                                                     \
+            out[(size_t)0 * ld + k] = in[(size_t)0 * ld + k];                        \
+            out[(size_t)(n + 1) * ld + k] = in[(size_t)(n + 1) * ld + k];            \
+            out[(size_t)k * ld + 0] = in[(size_t)k * ld + 0];                        \
+            out[(size_t)k * ld + n + 1] = in[(size_t)k * ld + n + 1];                \
+        }                                                                            \
+    }                                                                                \
+}                                                                                    \
+                                                                                     \
+/* Generic 3x3 stencil: out(i,j) = scale * S(phi)(i,j), out is n x ld_out. */        \
+void ox_apply_stencil_##SUF(const ST *phi, int n, int ld, const double taps[9],      \
+                            double scale, int bc, ST *out, int ld_out)               \
+{                                                                                    \
+    AT *w = ghosted_copy_##SUF(phi, n, ld, bc);                                      \
+    AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
+    stencil_pass_##SUF(w, n, taps, temp);                                            \
+    AT sc = (AT)scale;                                                               \
+    for (int i = 0; i < n; ++i)                                                      \
+        for (int j = 0; j < n; ++j)                                                  \
+            out[(size_t)i * ld_out + j] = STORE(sc * temp[(size_t)i * n + j]);       \
+    free(temp);                                                                      \
+    free(w);                                                                         \
+}                                                                                    \
+                                                                                     \
+/* Residual of phi: r = f - (1/h^2) S(phi); norms of r; r_out optional. */          \
+void ox_residual_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,          \
+                       double h, int bc, ST *r_out, int ld_r, double *norms)         \
+{                                                                                    \
+    static const double lap[9] = {0, 1, 0, 1, -4, 1, 0, 1, 0};                       \
+    AT c = (AT)(1.0 / (h * h));                                                      \
+    AT *w = ghosted_copy_##SUF(phi, n, ld, bc);                                      \
+    AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
+    stencil_pass_##SUF(w, n, lap, temp);                                             \
+    norm_pass_##SUF(temp, n, f, ld_f, c, r_out, ld_r, norms);                        \
+    free(temp);                                                                      \
+    free(w);                                                                         \
+}                                                                                    \
+                                                                                     \
+/* One sweep in -> out (the three steps of the algorithm, then the output ghosts). \
+ * norms (optional) receives the norm of the residual of the INPUT iterate. */      \
+void ox_sweep_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,     \
+                    double h, double lambda, int bc, double *norms)                  \
+{                                                                                    \
+    static const double lap[9] = {0, 1, 0, 1, -4, 1, 0, 1, 0};                       \
+    AT c = (AT)(1.0 / (h * h));                                                      \
+    AT wgt = (AT)(lambda / (h * h));                                                 \
+    AT lam = (AT)lambda;                                                             \
+    int m = n + 2;                                                                   \
+    AT *w = ghosted_copy_##SUF(in, n, ld, bc);                                       \
+    AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
+    /* (1) Laplacian */                                                              \
+    stencil_pass_##SUF(w, n, lap, temp);                                             \
+    /* (2) Jacobi update (1, w, -lambda) on [phi; S phi; rho] */                     \
+    for (int i = 1; i <= n; ++i)                                                     \
+        for (int j = 1; j <= n; ++j) {                                               \
+            AT p = w[(size_t)i * m + j];                                             \
+            AT s = temp[(size_t)(i - 1) * n + (j - 1)];                              \
+            AT rho = LOAD(f[(size_t)(i - 1) * ld_f + (j - 1)]);                      \
+            out[(size_t)i * ld + j] = STORE((p + wgt * s) - lam * rho);              \
+        }                                                                            \
+    /* (3) max-norm of the input iterate's residual */                               \
+    if (norms) norm_pass_##SUF(temp, n, f, ld_f, c, NULL, 0, norms);                 \
+    write_out_ghosts_##SUF(in, out, n, ld, bc);                                      \
+    free(temp);                                                                      \
+    free(w);                                                                         \
+}                                                                                    \
+                                                                                     \
+/* nsweeps sweeps in -> out (in is not modified; out gets the final iterate).       \
+ * resmode LAGGED: norms of the last sweep's input; FINAL: norms of out.            \
+ * nsweeps == 0 copies in to out.  The four corner cells of out are never         \
+ * written (the 5-point stencil does not read them). */                                       \
+void ox_relax_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,     \
+                    double h, double lambda, int nsweeps, int bc, int resmode,       \
+                    double *norms)                                                   \
+{                                                                                    \
+    int m = n + 2;                                                                   \
+    size_t total = (size_t)(m - 1) * ld + m;                                         \
+    ST *a = (ST *)malloc(sizeof(ST) * total);                                        \
+    ST *b = (ST *)malloc(sizeof(ST) * total);                                        \
+    memcpy(a, in, sizeof(ST) * total);                                               \
+    memcpy(b, in, sizeof(ST) * total);                                               \
+    for (int it = 0; it < nsweeps; ++it) {                                           \
+        double *nrm = (resmode == OX_RES_LAGGED && it == nsweeps - 1) ? norms : NULL;\
+        ox_sweep_##SUF(a, b, n, ld, f, ld_f, h, lambda, bc, nrm);                    \
+        ST *t = a; a = b; b = t;                                                     \
+    }                                                                                \
+    for (int i = 0; i < m; ++i)                                                      \
+        for (int j = 0; j < m; ++j) {                                                \
+            int corner = (i == 0 || i == m - 1) && (j == 0 || j == m - 1);           \
+            if (!corner) out[(size_t)i * ld + j] = a[(size_t)i * ld + j];            \
+        }                                                                            \
+    if (resmode == OX_RES_FINAL)                                                     \
+        ox_residual_##SUF(a, n, ld, f, ld_f, h, bc, NULL, 0, norms);                 \
+    free(a);                                                                         \
+    free(b);                                                                         \
+}
+
+#define ID(x) (x)
+OX_DEFINE(f64, double, double, ID, ID)
+OX_DEFINE(f32, float, float, ID, ID)
+OX_DEFINE(bf16, uint16_t, float, ox_bf16_to_f32, ox_f32_to_bf16)
+
+/* ================================================================== */
+/* Mixed-precision iterative refinement (an extension beyond the paper: */
+/* the relaxation of the paper run on the error equation).              */
+/*                                                                      */
+/* Outer step in FP64:   r = f - L phi  (the FP64 residual above),      */
+/*                       stop when max|r| <= rtol * max|f|;             */
+/* inner solve in low precision:  L delta = r  by k_in plain Jacobi     */
+/*                       sweeps from delta = 0 (storage per variant);   */
+/* update in FP64:       phi = phi + delta.                             */
+/* lowp: 1 = FP32 storage and arithmetic, 2 = BF16 storage, FP32 math.  */
+/* Returns the number of outer steps taken; norms of the last residual  */
+/* in norms[0..1]; phi is updated in place.                             */
+/* ================================================================== */
+int ox_refine(double *phi, int n, int ld, const double *f, int ld_f, double h,
+              double lambda, int bc, int lowp, int k_in, int max_outer,
+              double rtol, double *norms)
+{
+    int m = n + 2;
+    size_t total = (size_t)(m - 1) * ld + m;
+    double fmax = 0.0;
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) fmax = nanmax_d(fmax, fabs(f[(size_t)i * ld_f + j]));
+    double *r = (double *)malloc(sizeof(double) * (size_t)n * n);
+    /* low-precision buffers: delta (ghosted, same ld) and its right-hand side */
+    void *d_in = calloc(total, lowp == 1 ? 4 : 2);
+    void *d_out = calloc(total, lowp == 1 ? 4 : 2);
+    void *rl = calloc((size_t)n * n, lowp == 1 ? 4 : 2);
+    int outer = 0;
+    for (;;) {
+        ox_residual_f64(phi, n, ld, f, ld_f, h, bc, r, n, norms);
+        int converged = norms[0] <= rtol * fmax;
+        if (converged || isnan(norms[0]) || outer >= max_outer) break;
+        /* r rounded into the inner right-hand side: FP64 -> FP32 (-> BF16) */
+        for (size_t q = 0; q < (size_t)n * n; ++q) {
+            if (lowp == 1) ((float *)rl)[q] = (float)r[q];
+            else ((uint16_t *)rl)[q] = ox_f32_to_bf16((float)r[q]);
+        }
+        /* delta starts at zero, ghosts included (the error of a fixed ghost is 0) */
+        memset(d_in, 0, total * (lowp == 1 ? 4 : 2));
+        if (lowp == 1)
+            ox_relax_f32((const float *)d_in, (float *)d_out, n, ld, (const float *)rl, n,
+                         h, lambda, k_in, bc, OX_RES_NONE, NULL);
+        else
+            ox_relax_bf16((const uint16_t *)d_in, (uint16_t *)d_out, n, ld,
+                          (const uint16_t *)rl, n, h, lambda, k_in, bc, OX_RES_NONE, NULL);
+        for (int i = 1; i <= n; ++i)
+            for (int j = 1; j <= n; ++j) {
+                size_t q = (size_t)i * ld + j;
+                double dv = (lowp == 1) ? (double)((float *)d_out)[q]
+                                        : (double)ox_bf16_to_f32(((uint16_t *)d_out)[q]);
+                phi[q] = phi[q] + dv;
+            }
+        ++outer;
+    }
+    free(r);
+    free(d_in);
+    free(d_out);
+    free(rl);
+    return outer;
+}
+
+/* Array form of the bfloat16 rounding above (for preparing test inputs). */
+void ox_f32_to_bf16_array(const float *x, uint16_t *y, size_t count)
+{
+    for (size_t q = 0; q < count; ++q) y[q] = ox_f32_to_bf16(x[q]);
+}
