@@ -1,0 +1,197 @@
+/*
+ * protox.h -- C ABI of the MI355X (gfx950) fused Poisson relaxation library.
+ *
+ * The operations follow Section IV of the ProtoX paper ("2D Poisson
+ * equation", "Algorithm", the OL expressions and the generated fused code):
+ *
+ *   stencil    S(phi)(i,j) = sum_{a,b in -1..1} t[a][b] phi(i+a, j+b)   (Eq. 1)
+ *              with the 5-point filter t = [0,1,0; 1,-4,1; 0,1,0];
+ *   Laplacian  L = S / h^2, the discretisation of Eq. 2;
+ *   Jacobi     phi' = (phi + w s) - lambda f,  s = S(phi), w = lambda / h^2
+ *              (Eq. 3 in the OL form (1, w, -lambda) on [phi; S phi; rho]);
+ *   residual   r = f - (1/h^2) s, reported as max|r| (the max-norm of the
+ *              OL norm expression; NaN-propagating) and sum r^2.
+ *
+ * The right-hand side is called f here (rho in the paper).
+ *
+ * Data layout (all grids row-major, column index fastest):
+ *   phi  (n+2) rows x ld elements, ld >= n+2; interior cells at rows and
+ *        columns 1..n, one ghost layer around them.  The buffer must hold
+ *        (n+2)*ld elements.
+ *   f    n rows x ld_f elements, ld_f >= n; f[(i-1)*ld_f + (j-1)] belongs to
+ *        phi cell (i, j).  The buffer must hold n*ld_f elements.
+ *   out/r/temp of stencil and residual calls: n rows x ld_x, compact like f.
+ * Grid spacing h = 1/n for the cell-centred unit square (the caller passes h).
+ *
+ * Boundary handling (px_bc):
+ *   PX_BC_DIRICHLET0   homogeneous Dirichlet at the cell faces: every sweep
+ *                      reads ghost = -(adjacent interior) (odd reflection),
+ *                      whatever the ghost ring holds; outputs of relax calls
+ *                      get their edge ghosts written the same way.
+ *   PX_BC_GHOST_FIXED  the ghost ring is read as given and never changes
+ *                      (the paper's generated code reads ghosts and never
+ *                      writes them); relax copies it to the output.
+ *   The four corner cells of a phi output are never written (the 5-point
+ *   stencil does not read them).  For general 3x3 taps under DIRICHLET0 the
+ *   corner ghost is +(diagonal interior) (reflection in both directions).
+ *
+ * Element types (px_dtype): FP64, FP32, BF16 (bfloat16 storage, FP32
+ * arithmetic, round-to-nearest-even on every store).  Arithmetic follows the
+ * association above with no fused multiply-add, so results are reproducible
+ * bit for bit; the FP32/BF16 constants w, 1/h^2 and lambda are computed in
+ * FP64 and rounded once.
+ *
+ * Ownership and ordering: every pointer argument named as device memory is
+ * owned by the caller and never freed by the library.  Calls enqueue work on
+ * `stream` (a hipStream_t; NULL = the default stream) and return without
+ * waiting, except px_solve, which waits on the stream to read norms.
+ * A px_ctx owns scratch device memory (ping-pong grid, reduction partials)
+ * and must not be used by two calls that may run concurrently.
+ *
+ * Errors: every function returns a px_status.  Arguments are validated on
+ * the host before any HIP call; on failure nothing is enqueued and
+ * px_last_error() (thread-local) describes the problem.  HIP failures map to
+ * PX_EHIP.  No exception or abort crosses this interface.
+ */
+#ifndef PROTOX_H
+#define PROTOX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum px_status {
+    PX_OK = 0,
+    PX_EINVAL = -1,        /* bad size, pointer, alignment, enum or value    */
+    PX_EUNSUPPORTED = -2,  /* valid request this build does not implement    */
+    PX_EALIAS = -3,        /* an output overlaps an input it must not alias  */
+    PX_EHIP = -4,          /* the HIP runtime reported an error              */
+    PX_ENOTCONV = -5,      /* px_solve: max_sweeps reached before tolerance  */
+    PX_EDIVERGED = -6,     /* px_solve: residual grew beyond recovery        */
+    PX_ENONFINITE = -7,    /* px_solve: NaN or Inf in the residual           */
+    PX_ENOMEM = -8         /* scratch allocation failed                      */
+} px_status;
+
+typedef enum px_dtype { PX_F64 = 0, PX_F32 = 1, PX_BF16 = 2 } px_dtype;
+typedef enum px_bc { PX_BC_DIRICHLET0 = 0, PX_BC_GHOST_FIXED = 1 } px_bc;
+typedef enum px_resmode {
+    PX_RES_NONE = 0,   /* no norms                                              */
+    PX_RES_LAGGED = 1, /* norms of the residual of the LAST sweep's input, the  */
+                       /* quantity the paper's fused loop computes              */
+    PX_RES_FINAL = 2   /* norms of the residual of phi_out (the Proto order)    */
+} px_resmode;
+
+typedef struct px_ctx px_ctx;
+
+/* Context on HIP device `device`; *out receives it.  Allocates nothing yet. */
+int px_ctx_create(int device, px_ctx **out);
+/* Frees the context's scratch (waits for the device first). NULL is a no-op. */
+int px_ctx_destroy(px_ctx *ctx);
+/* Pre-allocates the scratch a relax/solve call on an (n, ld, dtype) grid
+ * needs, so that later calls allocate nothing. */
+int px_ctx_reserve(px_ctx *ctx, int n, int ld, int dtype);
+/* Rows per tile of the fused relaxation kernel (0 = built-in heuristic).
+ * A tuning knob; any value in [1, 4096] gives identical results. */
+int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *px_last_error(void);
+const char *px_version(void);
+
+/*
+ * Stencil (Eq. 1): out(i,j) = scale * S(phi)(i,j) for the n x n interior,
+ * taps[3*(a+1) + (b+1)] = t[a][b] (host array of 9 doubles, row a = -1 is
+ * the row above).  Taps are visited in the order (-1,0), (0,0), (0,-1),
+ * (0,1), (1,0), then the corners; zero taps are skipped, so for the 5-point
+ * Laplacian the sum is ((((N - 4C) + W) + E) + S), the order of the paper's
+ * generated code.  scale == 1 skips the multiplication.
+ * phi: device, (n+2) x ld; out: device, n x ld_out.  phi and out must not
+ * overlap (PX_EALIAS).
+ */
+int px_apply_stencil(const void *phi, int n, int ld, int dtype, void *out, int ld_out,
+                     const double *taps, double scale, int bc, void *stream);
+
+/*
+ * Residual (the OL max-norm expression): r = f - (1/h^2) S(phi) over the
+ * interior, S the 5-point stencil.  r (device, n x ld_r, same dtype; may be
+ * NULL) receives the residual; norms (device, 2 doubles) receives
+ * { max|r|, sum r^2 }, both accumulated in FP64 (max NaN-propagating).
+ * Needs ctx for reduction scratch.
+ */
+int px_residual(const void *phi, int n, int ld, int dtype, const void *f, int ld_f, double h,
+                int bc, void *r, int ld_r, double *norms, px_ctx *ctx, void *stream);
+
+/*
+ * The pointwise Jacobi step on its own (the unfused form, Proto's
+ * forallInPlace): phi(i,j) = (phi(i,j) + w s(i,j)) - lambda f(i,j) in place
+ * over the interior, with s (device, n x ld_s) the unscaled stencil of phi
+ * from px_apply_stencil and w = lambda / h^2.  Ghosts are not touched.
+ */
+int px_jacobi_update(void *phi, int n, int ld, int dtype, const void *s, int ld_s,
+                     const void *f, int ld_f, double h, double lambda, void *stream);
+
+/*
+ * Fused relaxation: nsweeps damped-Jacobi sweeps phi_in -> phi_out, each
+ * sweep computing the stencil, the update and (on the sweep resmode asks
+ * for) the residual norms in one pass over memory.  Several sweeps run per
+ * kernel launch (temporal blocking): tblock in 1..8 sweeps per launch, 0 =
+ * library default.  Results do not depend on tblock or on the tile shape.
+ * phi_in is read-only; phi_out receives the final iterate, its edge ghosts
+ * per bc; both (n+2) x ld of dtype, non-overlapping (PX_EALIAS); f must not
+ * overlap phi_out.  nsweeps == 0 copies phi_in to phi_out (corners
+ * excepted).  norms: device, 2 doubles, required unless resmode is
+ * PX_RES_NONE.  Needs ctx (ping-pong buffer when more than one launch is
+ * needed, reduction partials).
+ */
+int px_relax_fused(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f,
+                   int ld_f, double h, double lambda, int nsweeps, int tblock, int bc,
+                   int resmode, double *norms, px_ctx *ctx, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Iterative solve (the paper's Algorithm iterated to a tolerance).         */
+/* ---------------------------------------------------------------------- */
+typedef enum px_mode {
+    PX_SOLVE_PLAIN = 0,      /* fused relaxation in phi's own precision           */
+    PX_SOLVE_MIXED_F32 = 1,  /* FP64 refinement around FP32 inner sweeps          */
+    PX_SOLVE_MIXED_BF16 = 2  /* FP64 refinement around BF16-storage inner sweeps  */
+} px_mode;
+
+typedef struct px_solve_opts {
+    int mode;              /* px_mode                                            */
+    int norm;              /* 0: stop on max-norm, 1: on the L2 norm             */
+    double rtol;           /* stop when ||r|| <= rtol * ||f|| (same norm)        */
+    int64_t max_sweeps;    /* sweep budget (inner sweeps for MIXED modes)        */
+    int check_every;       /* sweeps between residual checks (PLAIN)             */
+    int inner_sweeps;      /* sweeps per inner solve (MIXED)                     */
+    int tblock;            /* sweeps per launch, 0 = default                     */
+    int bc;                /* px_bc                                              */
+} px_solve_opts;
+
+typedef struct px_solve_stats {
+    int64_t sweeps;        /* sweeps performed                                   */
+    int64_t outer_steps;   /* refinement steps (MIXED) or checks (PLAIN)         */
+    double res_max;        /* final max|r|                                       */
+    double res_l2;         /* final sqrt(sum r^2)                                */
+    double rel_res_max;    /* res_max / max|f|                                   */
+    double rel_res_l2;     /* res_l2 / ||f||_2                                   */
+    double seconds;        /* host wall time inside px_solve                     */
+} px_solve_stats;
+
+/*
+ * Solve L phi = f from the given phi (in place, FP64 storage for the MIXED
+ * modes, any dtype for PLAIN), stopping at the tolerance, on NaN/Inf
+ * (PX_ENONFINITE), on growth of the residual by 1e8 over its start
+ * (PX_EDIVERGED) or at max_sweeps (PX_ENOTCONV).  f is in phi's dtype
+ * (FP64 for MIXED).  Waits on `stream` at every check.  stats may be NULL.
+ */
+int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, double h,
+             double lambda, const px_solve_opts *opts, px_solve_stats *stats, px_ctx *ctx,
+             void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PROTOX_H */

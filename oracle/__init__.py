@@ -60,7 +60,8 @@ def lib() -> ctypes.CDLL:
             getattr(L, f"ox_residual_{suf}").argtypes = [P, I, I, P, I, D, I, P, I, P]
             getattr(L, f"ox_sweep_{suf}").argtypes = [P, P, I, I, P, I, D, D, I, P]
             getattr(L, f"ox_relax_{suf}").argtypes = [P, P, I, I, P, I, D, D, I, I, I, P]
-            for nm in ("apply_stencil", "residual", "sweep", "relax"):
+            getattr(L, f"ox_relax_sides_{suf}").argtypes = [P, P, I, I, P, I, D, D, I, P, I, P]
+            for nm in ("apply_stencil", "residual", "sweep", "relax", "relax_sides"):
                 getattr(L, f"ox_{nm}_{suf}").restype = None
         L.ox_refine.argtypes = [P, I, I, P, I, D, D, I, I, I, I, D, P]
         L.ox_refine.restype = I
@@ -144,6 +145,22 @@ def relax(phi, f, n, h, lam, nsweeps, bc=BC_DIRICHLET0, resmode=RES_FINAL, out=N
     getattr(lib(), f"ox_relax_{_suffix(phi)}")(
         _ptr(phi), _ptr(out), n, phi.shape[1], _ptr(f), f.shape[1], float(h), float(lam),
         int(nsweeps), bc, resmode, _ptr(norms))
+    return out, float(norms[0]), float(norms[1])
+
+
+def relax_sides(phi, f, n, h, lam, nsweeps, bcs, resmode=RES_FINAL, out=None):
+    """Like relax() with one boundary mode per side: bcs = (north, south, west, east).
+    A GHOST_FIXED side holds its ghost layer as given (a box interface)."""
+    _check_phi(phi, n)
+    _check_f(f, n)
+    assert f.dtype == phi.dtype and len(bcs) == 4
+    if out is None:
+        out = np.zeros_like(phi)
+    b4 = np.ascontiguousarray(bcs, dtype=np.int32)
+    norms = np.full(2, np.nan, dtype=np.float64)
+    getattr(lib(), f"ox_relax_sides_{_suffix(phi)}")(
+        _ptr(phi), _ptr(out), n, phi.shape[1], _ptr(f), f.shape[1], float(h), float(lam),
+        int(nsweeps), _ptr(b4), resmode, _ptr(norms))
     return out, float(norms[0]), float(norms[1])
 
 

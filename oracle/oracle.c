@@ -107,26 +107,33 @@ static const int TAP_ORDER[9][2] = {
 /* ================================================================== */
 #define OX_DEFINE(SUF, ST, AT, LOAD, STORE)                                          \
                                                                                      \
-/* Step 0: a working copy of phi with the ghost ring refreshed per the BC. */       \
-static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, int bc)                 \
+/* Step 0: a working copy of phi with the ghost ring refreshed per side.          \
+ * bcs[0..3] = mode of the north (row 0), south (row n+1), west (column 0) and    \
+ * east (column n+1) ghost layers.  Corners are reflected only where both        \
+ * adjacent sides reflect. */                                                     \
+static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, const int bcs[4])       \
 {                                                                                    \
     int m = n + 2;                                                                   \
     AT *w = (AT *)malloc(sizeof(AT) * (size_t)m * m);                                \
     for (int i = 0; i < m; ++i)                                                      \
         for (int j = 0; j < m; ++j)                                                  \
             w[(size_t)i * m + j] = LOAD(phi[(size_t)i * ld + j]);                    \
-    if (bc == OX_BC_DIRICHLET0) {                                                    \
-        for (int k = 1; k <= n; ++k) {                                               \
-            w[(size_t)0 * m + k] = -w[(size_t)1 * m + k];                            \
+    for (int k = 1; k <= n; ++k) {                                                   \
+        if (bcs[0] == OX_BC_DIRICHLET0) w[(size_t)0 * m + k] = -w[(size_t)1 * m + k];\
+        if (bcs[1] == OX_BC_DIRICHLET0)                                              \
             w[(size_t)(n + 1) * m + k] = -w[(size_t)n * m + k];                      \
-            w[(size_t)k * m + 0] = -w[(size_t)k * m + 1];                            \
+        if (bcs[2] == OX_BC_DIRICHLET0) w[(size_t)k * m + 0] = -w[(size_t)k * m + 1];\
+        if (bcs[3] == OX_BC_DIRICHLET0)                                              \
             w[(size_t)k * m + (n + 1)] = -w[(size_t)k * m + n];                      \
-        }                                                                            \
-        w[0] = w[(size_t)1 * m + 1];                                                 \
-        w[n + 1] = w[(size_t)1 * m + n];                                             \
-        w[(size_t)(n + 1) * m + 0] = w[(size_t)n * m + 1];                           \
-        w[(size_t)(n + 1) * m + n + 1] = w[(size_t)n * m + n];                       \
     }                                                                                \
+    if (bcs[0] == OX_BC_DIRICHLET0 && bcs[2] == OX_BC_DIRICHLET0)                    \
+        w[0] = w[(size_t)1 * m + 1];                                                 \
+    if (bcs[0] == OX_BC_DIRICHLET0 && bcs[3] == OX_BC_DIRICHLET0)                    \
+        w[n + 1] = w[(size_t)1 * m + n];                                             \
+    if (bcs[1] == OX_BC_DIRICHLET0 && bcs[2] == OX_BC_DIRICHLET0)                    \
+        w[(size_t)(n + 1) * m + 0] = w[(size_t)n * m + 1];                           \
+    if (bcs[1] == OX_BC_DIRICHLET0 && bcs[3] == OX_BC_DIRICHLET0)                    \
+        w[(size_t)(n + 1) * m + n + 1] = w[(size_t)n * m + n];                       \
     return w;                                                                        \
 }                                                                                    \
                                                                                      \
@@ -153,6 +160,21 @@ static void stencil_pass_##SUF(const AT *w, int n, const double taps[9], AT *tem
         }                                                                            \
 }                                                                                    \
                                                                                      \
+/* Step 1 for the 5-point Laplacian (the filter t of the OL Laplace expression):    \
+ * temp(i,j) = ((((N - 4C) + W) + E) + S), the generic pass above with the zero   \
+ * taps dropped and the unit taps' exact multiplications left out. */             \
+static void laplace_pass_##SUF(const AT *w, int n, AT *temp)                          \
+{                                                                                    \
+    int m = n + 2;                                                                   \
+    for (int i = 1; i <= n; ++i)                                                     \
+        for (int j = 1; j <= n; ++j) {                                               \
+            AT C = w[(size_t)i * m + j];                                             \
+            AT N = w[(size_t)(i - 1) * m + j], S = w[(size_t)(i + 1) * m + j];       \
+            AT W = w[(size_t)i * m + (j - 1)], E = w[(size_t)i * m + (j + 1)];       \
+            temp[(size_t)(i - 1) * n + (j - 1)] = (((N - (AT)4 * C) + W) + E) + S;   \
+        }                                                                            \
+}                                                                                    \
+                                                                                     \
 /* Step 3 (OL max-norm): r = f - c*s over the interior; norms[0] = max|r| (NaN      \
  * propagating), norms[1] = sum r^2 in FP64, row-major order.  r_out optional. */    \
 static void norm_pass_##SUF(const AT *temp, int n, const ST *f, int ld_f, AT c,      \
@@ -170,23 +192,19 @@ static void norm_pass_##SUF(const AT *temp, int n, const ST *f, int ld_f, AT c, 
     if (norms) { norms[0] = mx; norms[1] = sq; }                                     \
 }                                                                                    \
                                                                                      \
-/* Output ghost ring of a freshly written phi_out: odd reflection of the new       \
- * interior (DIRICHLET0), or the input's ghosts unchanged (GHOST_FIXED).  The      \
+/* Output ghost ring of a freshly written phi_out, per side: odd reflection of the \
+ * new interior (DIRICHLET0), or the input's ghosts unchanged (GHOST_FIXED).  The \
  * four corner cells are left untouched. */                                          \
-static void write_out_ghosts_##SUF(const ST *in, ST *out, int n, int ld, int bc)     \
+static void write_out_ghosts_##SUF(const ST *in, ST *out, int n, int ld, const int bcs[4]) \
 {                                                                                    \
     for (int k = 1; k <= n; ++k) {                                                   \
-        if (bc == OX_BC_DIRICHLET0) {                                                \
-            out[(size_t)0 * ld + k] = STORE(-LOAD(out[(size_t)1 * ld + k]));         \
-            out[(size_t)(n + 1) * ld + k] = STORE(-LOAD(out[(size_t)n * ld + k]));   \
-            out[(size_t)k * ld + 0] = STORE(-LOAD(out[(size_t)k * ld + 1]));         \
-            out[(size_t)k * ld + n + 1] = STORE(-LOAD(out[(size_t)k * ld + n]));     \
-        } else {                                                                     \
-            out[(size_t)0 * ld + k] = in[(size_t)0 * ld + k];                        \
-            out[(size_t)(n + 1) * ld + k] = in[(size_t)(n + 1) * ld + k];            \
-            out[(size_t)k * ld + 0] = in[(size_t)k * ld + 0];                        \
-            out[(size_t)k * ld + n + 1] = in[(size_t)k * ld + n + 1];                \
-        }                                                                            \
+        size_t g[4] = {(size_t)0 * ld + k, (size_t)(n + 1) * ld + k,                 \
+                       (size_t)k * ld + 0, (size_t)k * ld + n + 1};                  \
+        size_t a[4] = {(size_t)1 * ld + k, (size_t)n * ld + k,                       \
+                       (size_t)k * ld + 1, (size_t)k * ld + n};                      \
+        for (int side = 0; side < 4; ++side)                                         \
+            out[g[side]] = (bcs[side] == OX_BC_DIRICHLET0) ? STORE(-LOAD(out[a[side]])) \
+                                                           : in[g[side]];            \
     }                                                                                \
 }                                                                                    \
                                                                                      \
@@ -194,7 +212,8 @@ static void write_out_ghosts_##SUF(const ST *in, ST *out, int n, int ld, int bc)
 void ox_apply_stencil_##SUF(const ST *phi, int n, int ld, const double taps[9],      \
                             double scale, int bc, ST *out, int ld_out)               \
 {                                                                                    \
-    AT *w = ghosted_copy_##SUF(phi, n, ld, bc);                                      \
+    const int bcs[4] = {bc, bc, bc, bc};                                             \
+    AT *w = ghosted_copy_##SUF(phi, n, ld, bcs);                                     \
     AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
     stencil_pass_##SUF(w, n, taps, temp);                                            \
     AT sc = (AT)scale;                                                               \
@@ -206,33 +225,39 @@ void ox_apply_stencil_##SUF(const ST *phi, int n, int ld, const double taps[9], 
 }                                                                                    \
                                                                                      \
 /* Residual of phi: r = f - (1/h^2) S(phi); norms of r; r_out optional. */          \
-void ox_residual_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,          \
-                       double h, int bc, ST *r_out, int ld_r, double *norms)         \
+void ox_residual_sides_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,    \
+                             double h, const int bcs[4], ST *r_out, int ld_r,        \
+                             double *norms)                                          \
 {                                                                                    \
-    static const double lap[9] = {0, 1, 0, 1, -4, 1, 0, 1, 0};                       \
     AT c = (AT)(1.0 / (h * h));                                                      \
-    AT *w = ghosted_copy_##SUF(phi, n, ld, bc);                                      \
+    AT *w = ghosted_copy_##SUF(phi, n, ld, bcs);                                     \
     AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
-    stencil_pass_##SUF(w, n, lap, temp);                                             \
+    laplace_pass_##SUF(w, n, temp);                                                  \
     norm_pass_##SUF(temp, n, f, ld_f, c, r_out, ld_r, norms);                        \
     free(temp);                                                                      \
     free(w);                                                                         \
 }                                                                                    \
+void ox_residual_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,          \
+                       double h, int bc, ST *r_out, int ld_r, double *norms)         \
+{                                                                                    \
+    const int bcs[4] = {bc, bc, bc, bc};                                             \
+    ox_residual_sides_##SUF(phi, n, ld, f, ld_f, h, bcs, r_out, ld_r, norms);        \
+}                                                                                    \
                                                                                      \
 /* One sweep in -> out (the three steps of the algorithm, then the output ghosts). \
  * norms (optional) receives the norm of the residual of the INPUT iterate. */      \
-void ox_sweep_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,     \
-                    double h, double lambda, int bc, double *norms)                  \
+void ox_sweep_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,         \
+                          int ld_f, double h, double lambda, const int bcs[4],       \
+                          double *norms)                                             \
 {                                                                                    \
-    static const double lap[9] = {0, 1, 0, 1, -4, 1, 0, 1, 0};                       \
     AT c = (AT)(1.0 / (h * h));                                                      \
     AT wgt = (AT)(lambda / (h * h));                                                 \
     AT lam = (AT)lambda;                                                             \
     int m = n + 2;                                                                   \
-    AT *w = ghosted_copy_##SUF(in, n, ld, bc);                                       \
+    AT *w = ghosted_copy_##SUF(in, n, ld, bcs);                                      \
     AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
     /* (1) Laplacian */                                                              \
-    stencil_pass_##SUF(w, n, lap, temp);                                             \
+    laplace_pass_##SUF(w, n, temp);                                                  \
     /* (2) Jacobi update (1, w, -lambda) on [phi; S phi; rho] */                     \
     for (int i = 1; i <= n; ++i)                                                     \
         for (int j = 1; j <= n; ++j) {                                               \
@@ -243,18 +268,26 @@ void ox_sweep_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,
         }                                                                            \
     /* (3) max-norm of the input iterate's residual */                               \
     if (norms) norm_pass_##SUF(temp, n, f, ld_f, c, NULL, 0, norms);                 \
-    write_out_ghosts_##SUF(in, out, n, ld, bc);                                      \
+    write_out_ghosts_##SUF(in, out, n, ld, bcs);                                     \
     free(temp);                                                                      \
     free(w);                                                                         \
+}                                                                                    \
+void ox_sweep_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,     \
+                    double h, double lambda, int bc, double *norms)                  \
+{                                                                                    \
+    const int bcs[4] = {bc, bc, bc, bc};                                             \
+    ox_sweep_sides_##SUF(in, out, n, ld, f, ld_f, h, lambda, bcs, norms);            \
 }                                                                                    \
                                                                                      \
 /* nsweeps sweeps in -> out (in is not modified; out gets the final iterate).       \
  * resmode LAGGED: norms of the last sweep's input; FINAL: norms of out.            \
  * nsweeps == 0 copies in to out.  The four corner cells of out are never         \
- * written (the 5-point stencil does not read them). */                                       \
-void ox_relax_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,     \
-                    double h, double lambda, int nsweeps, int bc, int resmode,       \
-                    double *norms)                                                   \
+ * written (the 5-point stencil does not read them).  bcs: per-side modes      \
+ * (north, south, west, east); a GHOST_FIXED side models a box interface whose    \
+ * ghost layer was filled from a neighbouring box before the sweeps. */           \
+void ox_relax_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,         \
+                          int ld_f, double h, double lambda, int nsweeps,            \
+                          const int bcs[4], int resmode, double *norms)              \
 {                                                                                    \
     int m = n + 2;                                                                   \
     size_t total = (size_t)(m - 1) * ld + m;                                         \
@@ -264,7 +297,7 @@ void ox_relax_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,
     memcpy(b, in, sizeof(ST) * total);                                               \
     for (int it = 0; it < nsweeps; ++it) {                                           \
         double *nrm = (resmode == OX_RES_LAGGED && it == nsweeps - 1) ? norms : NULL;\
-        ox_sweep_##SUF(a, b, n, ld, f, ld_f, h, lambda, bc, nrm);                    \
+        ox_sweep_sides_##SUF(a, b, n, ld, f, ld_f, h, lambda, bcs, nrm);             \
         ST *t = a; a = b; b = t;                                                     \
     }                                                                                \
     for (int i = 0; i < m; ++i)                                                      \
@@ -273,9 +306,17 @@ void ox_relax_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,
             if (!corner) out[(size_t)i * ld + j] = a[(size_t)i * ld + j];            \
         }                                                                            \
     if (resmode == OX_RES_FINAL)                                                     \
-        ox_residual_##SUF(a, n, ld, f, ld_f, h, bc, NULL, 0, norms);                 \
+        ox_residual_sides_##SUF(a, n, ld, f, ld_f, h, bcs, NULL, 0, norms);          \
     free(a);                                                                         \
     free(b);                                                                         \
+}                                                                                    \
+void ox_relax_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,     \
+                    double h, double lambda, int nsweeps, int bc, int resmode,       \
+                    double *norms)                                                   \
+{                                                                                    \
+    const int bcs[4] = {bc, bc, bc, bc};                                             \
+    ox_relax_sides_##SUF(in, out, n, ld, f, ld_f, h, lambda, nsweeps, bcs, resmode,  \
+                         norms);                                                     \
 }
 
 #define ID(x) (x)

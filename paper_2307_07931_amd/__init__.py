@@ -1,0 +1,268 @@
+"""Python binding of the MI355X fused Poisson relaxation library (libprotox.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/protox.h``.  PyTorch provides
+device memory and streams.  If the shared library has not been built the
+import of any function fails loudly -- there is no CPU fallback.
+
+Layout conventions (Section IV of the ProtoX paper: an n x n box of cells with
+one ghost layer, m = n + 2):
+
+* ``phi``: 2-D tensor of shape (n+2, ld'), unit column stride, row stride ld
+  (ld >= n+2); interior at [1:n+1, 1:n+1].
+* ``f``: 2-D tensor of shape (n, >= n), unit column stride, row stride ld_f.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libprotox.so")
+
+# px_status
+OK, EINVAL, EUNSUPPORTED, EALIAS, EHIP, ENOTCONV, EDIVERGED, ENONFINITE, ENOMEM = 0, -1, -2, -3, -4, -5, -6, -7, -8
+STATUS_NAMES = {0: "PX_OK", -1: "PX_EINVAL", -2: "PX_EUNSUPPORTED", -3: "PX_EALIAS", -4: "PX_EHIP",
+                -5: "PX_ENOTCONV", -6: "PX_EDIVERGED", -7: "PX_ENONFINITE", -8: "PX_ENOMEM"}
+F64, F32, BF16 = 0, 1, 2
+BC_DIRICHLET0, BC_GHOST_FIXED = 0, 1
+RES_NONE, RES_LAGGED, RES_FINAL = 0, 1, 2
+SOLVE_PLAIN, SOLVE_MIXED_F32, SOLVE_MIXED_BF16 = 0, 1, 2
+LAPLACE_TAPS = (0.0, 1.0, 0.0, 1.0, -4.0, 1.0, 0.0, 1.0, 0.0)
+
+_DTYPE_CODE = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}
+
+
+class ProtoxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class _SolveOpts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("norm", ctypes.c_int), ("rtol", ctypes.c_double),
+                ("max_sweeps", ctypes.c_int64), ("check_every", ctypes.c_int),
+                ("inner_sweeps", ctypes.c_int), ("tblock", ctypes.c_int), ("bc", ctypes.c_int)]
+
+
+class _SolveStats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int64), ("outer_steps", ctypes.c_int64),
+                ("res_max", ctypes.c_double), ("res_l2", ctypes.c_double),
+                ("rel_res_max", ctypes.c_double), ("rel_res_l2", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+
+EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
+           "px_last_error", "px_version", "px_apply_stencil", "px_residual", "px_jacobi_update",
+           "px_relax_fused", "px_solve")
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libprotox.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2307_07931_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    L.px_ctx_create.argtypes = [I, ctypes.POINTER(P)]
+    L.px_ctx_destroy.argtypes = [P]
+    L.px_ctx_reserve.argtypes = [P, I, I, I]
+    L.px_ctx_set_tile_rows.argtypes = [P, I]
+    L.px_last_error.restype = ctypes.c_char_p
+    L.px_last_error.argtypes = []
+    L.px_version.restype = ctypes.c_char_p
+    L.px_version.argtypes = []
+    L.px_apply_stencil.argtypes = [P, I, I, I, P, I, ctypes.POINTER(D), D, I, P]
+    L.px_residual.argtypes = [P, I, I, I, P, I, D, I, P, I, P, P, P]
+    L.px_jacobi_update.argtypes = [P, I, I, I, P, I, P, I, D, D, P]
+    L.px_relax_fused.argtypes = [P, P, I, I, I, P, I, D, D, I, I, I, I, P, P, P]
+    L.px_solve.argtypes = [P, I, I, I, P, I, D, D, ctypes.POINTER(_SolveOpts),
+                           ctypes.POINTER(_SolveStats), P, P]
+    for nm in ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
+               "px_apply_stencil", "px_residual", "px_jacobi_update", "px_relax_fused", "px_solve"):
+        getattr(L, nm).restype = I
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        raise ProtoxError(status, lib().px_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().px_last_error().decode()
+
+
+def version() -> str:
+    return lib().px_version().decode()
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    try:
+        return _DTYPE_CODE[t.dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {t.dtype} (float64, float32, bfloat16)")
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, torch.cuda.Stream):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _ld(t: torch.Tensor, rows: int, min_cols: int, name: str) -> int:
+    if t.dim() != 2 or t.shape[0] != rows or t.shape[1] < min_cols or t.stride(1) != 1:
+        raise ValueError(f"{name}: expected a ({rows}, >={min_cols}) tensor with unit column stride, "
+                         f"got shape {tuple(t.shape)} strides {t.stride()}")
+    ld = t.stride(0)
+    need = (t.storage_offset() + rows * ld) * t.element_size()
+    if t.untyped_storage().nbytes() < need:
+        raise ValueError(f"{name}: storage holds fewer than rows*ld elements")
+    return ld
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+# ------------------------------------------------------------------ memory --
+
+def round_up(x: int, m: int) -> int:
+    return (x + m - 1) // m * m
+
+
+def alloc_grid(n: int, dtype=torch.float64, device="cuda", ld: int | None = None) -> torch.Tensor:
+    """Zeroed (n+2) x ld grid; default ld = n+2 rounded up to 128 bytes."""
+    es = torch.empty(0, dtype=dtype).element_size()
+    ld = ld or round_up(n + 2, 128 // es)
+    return torch.zeros((n + 2, ld), dtype=dtype, device=device)
+
+
+def alloc_rhs(n: int, dtype=torch.float64, device="cuda", ld_f: int | None = None) -> torch.Tensor:
+    """Zeroed n x ld_f right-hand side placed one element past a 256-byte boundary,
+    so that its columns line up with a grid's interior columns for vector loads."""
+    es = torch.empty(0, dtype=dtype).element_size()
+    ld_f = ld_f or round_up(n + 2, 128 // es)
+    pad = 256 // es
+    base = torch.zeros(n * ld_f + pad, dtype=dtype, device=device)
+    return base[1:1 + n * ld_f].view(n, ld_f)
+
+
+# ----------------------------------------------------------------- context --
+
+class Context:
+    """Owns a px_ctx (scratch memory for relaxation and reductions)."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        h = ctypes.c_void_p()
+        _check(lib().px_ctx_create(int(device), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def reserve(self, n: int, ld: int, dtype: int):
+        _check(lib().px_ctx_reserve(self._h, n, ld, dtype))
+
+    def set_tile_rows(self, rows: int):
+        _check(lib().px_ctx_set_tile_rows(self._h, int(rows)))
+
+    def close(self):
+        if self._h:
+            lib().px_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------------- operations --
+
+def apply_stencil(phi, n, out, taps=LAPLACE_TAPS, scale=1.0, bc=BC_DIRICHLET0, stream=None):
+    """out = scale * S(phi) over the interior (Eq. 1, 3x3 taps)."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    ldo = _ld(out, n, n, "out")
+    if out.dtype != phi.dtype:
+        raise TypeError("out must have phi's dtype")
+    t = (ctypes.c_double * 9)(*[float(x) for x in taps])
+    _check(lib().px_apply_stencil(_ptr(phi), n, ld, dtype_code(phi), _ptr(out), ldo, t, float(scale),
+                                  int(bc), _stream_handle(stream)))
+    return out
+
+
+def residual(phi, n, f, h, norms, ctx: Context, bc=BC_DIRICHLET0, r=None, stream=None):
+    """r = f - (1/h^2) S(phi); norms (float64 device tensor of 2) <- {max|r|, sum r^2}."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    ldf = _ld(f, n, n, "f")
+    ldr = _ld(r, n, n, "r") if r is not None else 0
+    _check(lib().px_residual(_ptr(phi), n, ld, dtype_code(phi), _ptr(f), ldf, float(h), int(bc),
+                             _ptr(r), ldr, _ptr(norms), ctx.handle, _stream_handle(stream)))
+    return norms
+
+
+def jacobi_update(phi, n, s, f, h, lam, stream=None):
+    """In place: phi = (phi + (lam/h^2) s) - lam f over the interior (unfused step)."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    lds = _ld(s, n, n, "s")
+    ldf = _ld(f, n, n, "f")
+    _check(lib().px_jacobi_update(_ptr(phi), n, ld, dtype_code(phi), _ptr(s), lds, _ptr(f), ldf,
+                                  float(h), float(lam), _stream_handle(stream)))
+    return phi
+
+
+def relax_fused(phi_in, phi_out, n, f, h, lam, nsweeps, ctx: Context, tblock=0,
+                bc=BC_DIRICHLET0, resmode=RES_FINAL, norms=None, stream=None):
+    """nsweeps fused damped-Jacobi sweeps phi_in -> phi_out (tblock sweeps per launch)."""
+    ld = _ld(phi_in, n + 2, n + 2, "phi_in")
+    if _ld(phi_out, n + 2, n + 2, "phi_out") != ld:
+        raise ValueError("phi_in and phi_out must share ld")
+    ldf = _ld(f, n, n, "f")
+    _check(lib().px_relax_fused(_ptr(phi_in), _ptr(phi_out), n, ld, dtype_code(phi_in), _ptr(f), ldf,
+                                float(h), float(lam), int(nsweeps), int(tblock), int(bc), int(resmode),
+                                _ptr(norms), ctx.handle, _stream_handle(stream)))
+    return phi_out
+
+
+@dataclass
+class SolveStats:
+    status: int
+    sweeps: int
+    outer_steps: int
+    res_max: float
+    res_l2: float
+    rel_res_max: float
+    rel_res_l2: float
+    seconds: float
+
+
+def solve(phi, n, f, h, lam, ctx: Context, mode=SOLVE_PLAIN, rtol=1e-10, norm=0,
+          max_sweeps=10 ** 9, check_every=0, inner_sweeps=0, tblock=0, bc=BC_DIRICHLET0,
+          stream=None, raise_on_error=True) -> SolveStats:
+    """Iterate to ||r|| <= rtol ||f|| in place on phi; returns the solve statistics."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    ldf = _ld(f, n, n, "f")
+    o = _SolveOpts(int(mode), int(norm), float(rtol), int(max_sweeps), int(check_every),
+                   int(inner_sweeps), int(tblock), int(bc))
+    s = _SolveStats()
+    st = lib().px_solve(_ptr(phi), n, ld, dtype_code(phi), _ptr(f), ldf, float(h), float(lam),
+                        ctypes.byref(o), ctypes.byref(s), ctx.handle, _stream_handle(stream))
+    if st != OK and raise_on_error:
+        _check(st)
+    return SolveStats(st, s.sweeps, s.outer_steps, s.res_max, s.res_l2, s.rel_res_max, s.rel_res_l2,
+                      s.seconds)

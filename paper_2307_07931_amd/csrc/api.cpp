@@ -1,0 +1,525 @@
+// api.cpp -- the C ABI declared in include/protox.h: argument validation (on
+// the host, before any HIP call), the context and its scratch memory, launch
+// sequencing for multi-launch relaxation, and the host-driven solve loop.
+#include "../../include/protox.h"
+#include "px_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+using namespace px;
+
+struct px_ctx {
+    int device = 0;
+    int tile_rows = 0;
+    // ping-pong grid (any dtype) for multi-launch relaxation
+    void *grid = nullptr;
+    size_t grid_bytes = 0;
+    // reduction partials: count slots of (u64 max bits, double sum)
+    unsigned long long *pmax = nullptr;
+    double *psum = nullptr;
+    size_t part_count = 0;
+    // solve: device norms, pinned host copy, norms of f
+    double *norms_dev = nullptr;
+    double *norms_host = nullptr;
+    // mixed precision: FP64 second grid, two low-precision ghosted grids, low r
+    void *mix = nullptr;
+    size_t mix_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(PX_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define PX_HIP(call, what)                                                                        \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return hip_fail(e_, what);                                          \
+    } while (0)
+
+constexpr int MAX_N = 1 << 17;
+
+bool valid_dtype(int d) { return d == F64 || d == F32 || d == BF16; }
+bool valid_bc(int b) { return b == DIRICHLET0 || b == GHOST_FIXED; }
+
+size_t grid_bytes(int n, int ld, int dtype) { return (size_t)(n + 2) * (size_t)ld * elem_size(dtype); }
+size_t flat_bytes(int n, int ld, int dtype) { return (size_t)n * (size_t)ld * elem_size(dtype); }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + nb && y < x + na;
+}
+
+int check_n_ld(int n, int ld, int dtype)
+{
+    if (!valid_dtype(dtype)) return fail(PX_EINVAL, "unknown dtype %d", dtype);
+    if (n < 1 || n > MAX_N) return fail(PX_EINVAL, "n = %d outside [1, %d]", n, MAX_N);
+    if (ld < n + 2) return fail(PX_EINVAL, "ld = %d < n + 2 = %d", ld, n + 2);
+    return PX_OK;
+}
+
+int check_ptr(const void *p, int dtype, const char *name)
+{
+    if (!p) return fail(PX_EINVAL, "%s is NULL", name);
+    if (reinterpret_cast<uintptr_t>(p) % (uintptr_t)elem_size(dtype))
+        return fail(PX_EINVAL, "%s is not aligned to its element size", name);
+    return PX_OK;
+}
+
+int check_flat(const void *p, int n, int ldx, int dtype, const char *name)
+{
+    int st = check_ptr(p, dtype, name);
+    if (st) return st;
+    if (ldx < n) return fail(PX_EINVAL, "leading dimension of %s (%d) < n (%d)", name, ldx, n);
+    return PX_OK;
+}
+
+int check_pos(double x, const char *name)
+{
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(PX_EINVAL, "%s must be positive and finite", name);
+    return PX_OK;
+}
+
+int set_device(px_ctx *ctx)
+{
+    PX_HIP(hipSetDevice(ctx->device), "hipSetDevice");
+    return PX_OK;
+}
+
+int ensure_grid(px_ctx *ctx, size_t bytes)
+{
+    if (ctx->grid_bytes >= bytes) return PX_OK;
+    if (ctx->grid) (void)hipFree(ctx->grid);
+    ctx->grid = nullptr;
+    ctx->grid_bytes = 0;
+    if (hipMalloc(&ctx->grid, bytes) != hipSuccess) return fail(PX_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    ctx->grid_bytes = bytes;
+    return PX_OK;
+}
+
+int ensure_partials(px_ctx *ctx, size_t count)
+{
+    if (ctx->part_count >= count) return PX_OK;
+    if (ctx->pmax) (void)hipFree(ctx->pmax);
+    if (ctx->psum) (void)hipFree(ctx->psum);
+    ctx->pmax = nullptr;
+    ctx->psum = nullptr;
+    ctx->part_count = 0;
+    if (hipMalloc(&ctx->pmax, count * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&ctx->psum, count * sizeof(double)) != hipSuccess)
+        return fail(PX_ENOMEM, "hipMalloc of %zu reduction partials failed", count);
+    ctx->part_count = count;
+    return PX_OK;
+}
+
+int ensure_norms(px_ctx *ctx)
+{
+    if (ctx->norms_dev) return PX_OK;
+    if (hipMalloc(&ctx->norms_dev, 8 * sizeof(double)) != hipSuccess)
+        return fail(PX_ENOMEM, "hipMalloc(norms) failed");
+    if (hipHostMalloc(&ctx->norms_host, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        return fail(PX_ENOMEM, "hipHostMalloc(norms) failed");
+    return PX_OK;
+}
+
+int ensure_mix(px_ctx *ctx, size_t bytes)
+{
+    if (ctx->mix_bytes >= bytes) return PX_OK;
+    if (ctx->mix) (void)hipFree(ctx->mix);
+    ctx->mix = nullptr;
+    ctx->mix_bytes = 0;
+    if (hipMalloc(&ctx->mix, bytes) != hipSuccess) return fail(PX_ENOMEM, "hipMalloc(%zu) failed", bytes);
+    ctx->mix_bytes = bytes;
+    return PX_OK;
+}
+
+int default_tblock(int dtype, int n)
+{
+    (void)dtype;
+    return n >= 256 ? 4 : 2;
+}
+
+Partials partials(px_ctx *ctx) { return Partials{ctx->pmax, ctx->psum}; }
+
+// Runs nsweeps sweeps: src -> ... -> dst, alternating between dst and tmp so the
+// last launch writes dst.  src is only read.  tmp may be NULL when one launch.
+int run_sweeps(px_ctx *ctx, int dtype, const void *src, void *dst, void *tmp, int n, int ld,
+               const void *f, int ld_f, double h, double lambda, int nsweeps, int k, int bc,
+               int resmode, double *norms, hipStream_t s)
+{
+    const int L = (nsweeps + k - 1) / k;
+    const double c = 1.0 / (h * h);
+    const double w = lambda / (h * h);
+    const void *cur = src;
+    int done = 0;
+    for (int i = 0; i < L; ++i) {
+        const int ks = std::min(k, nsweeps - done);
+        void *to = (((L - 1 - i) % 2) == 0) ? dst : tmp;
+        RelaxLaunch a;
+        a.in = cur;
+        a.out = to;
+        a.f = f;
+        a.n = n;
+        a.ld = ld;
+        a.ld_f = ld_f;
+        a.c = c;
+        a.w = w;
+        a.lam = lambda;
+        a.bc = bc;
+        a.sweeps = ks;
+        a.resmode = (i == L - 1) ? resmode : RES_NONE;
+        a.rows = ctx->tile_rows > 0 ? ctx->tile_rows : relax_default_rows(dtype, n, ks);
+        a.part = partials(ctx);
+        if (a.resmode != RES_NONE) {
+            int st = ensure_partials(ctx, (size_t)relax_num_waves(dtype, n, ks, a.resmode, a.rows));
+            if (st) return st;
+            a.part = partials(ctx);
+        }
+        PX_HIP(relax_launch(dtype, a, s), "relax kernel launch");
+        if (a.resmode != RES_NONE)
+            PX_HIP(reduce_partials(a.part, relax_num_waves(dtype, n, ks, a.resmode, a.rows), norms, s),
+                   "norm reduction launch");
+        cur = to;
+        done += ks;
+    }
+    return PX_OK;
+}
+
+int residual_into(px_ctx *ctx, int dtype, const void *phi, int n, int ld, const void *f, int ld_f,
+                  double h, int bc, void *r, int ld_r, double *norms, hipStream_t s)
+{
+    const int nblk = pointwise_num_blocks(n);
+    int st = ensure_partials(ctx, (size_t)nblk);
+    if (st) return st;
+    PX_HIP(residual_launch(dtype, phi, n, ld, f, ld_f, 1.0 / (h * h), bc, r, ld_r, partials(ctx), s),
+           "residual kernel launch");
+    PX_HIP(reduce_partials(partials(ctx), nblk, norms, s), "norm reduction launch");
+    return PX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *px_last_error(void) { return g_err.c_str(); }
+const char *px_version(void) { return "protox-mi355x 0.1 (gfx950)"; }
+
+int px_ctx_create(int device, px_ctx **out)
+{
+    if (!out) return fail(PX_EINVAL, "out is NULL");
+    if (device < 0) return fail(PX_EINVAL, "device %d < 0", device);
+    px_ctx *c = new (std::nothrow) px_ctx();
+    if (!c) return fail(PX_ENOMEM, "out of host memory");
+    c->device = device;
+    *out = c;
+    return PX_OK;
+}
+
+int px_ctx_destroy(px_ctx *ctx)
+{
+    if (!ctx) return PX_OK;
+    if (ctx->grid || ctx->pmax || ctx->norms_dev || ctx->mix) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        if (ctx->grid) (void)hipFree(ctx->grid);
+        if (ctx->pmax) (void)hipFree(ctx->pmax);
+        if (ctx->psum) (void)hipFree(ctx->psum);
+        if (ctx->norms_dev) (void)hipFree(ctx->norms_dev);
+        if (ctx->norms_host) (void)hipHostFree(ctx->norms_host);
+        if (ctx->mix) (void)hipFree(ctx->mix);
+    }
+    delete ctx;
+    return PX_OK;
+}
+
+int px_ctx_set_tile_rows(px_ctx *ctx, int rows)
+{
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if (rows < 0 || rows > 4096) return fail(PX_EINVAL, "tile rows %d outside [0, 4096]", rows);
+    ctx->tile_rows = rows;
+    return PX_OK;
+}
+
+int px_ctx_reserve(px_ctx *ctx, int n, int ld, int dtype)
+{
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = set_device(ctx))) return st;
+    if ((st = ensure_grid(ctx, grid_bytes(n, ld, dtype)))) return st;
+    size_t parts = (size_t)pointwise_num_blocks(n);
+    for (int k = 1; k <= 8; ++k)
+        for (int rm = RES_LAGGED; rm <= RES_FINAL; ++rm) {
+            const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : relax_default_rows(dtype, n, k);
+            parts = std::max(parts, (size_t)relax_num_waves(dtype, n, k, rm, rows));
+        }
+    if ((st = ensure_partials(ctx, parts))) return st;
+    return ensure_norms(ctx);
+}
+
+int px_apply_stencil(const void *phi, int n, int ld, int dtype, void *out, int ld_out,
+                     const double *taps, double scale, int bc, void *stream)
+{
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = check_ptr(phi, dtype, "phi"))) return st;
+    if ((st = check_flat(out, n, ld_out, dtype, "out"))) return st;
+    if (!taps) return fail(PX_EINVAL, "taps is NULL");
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(taps[k])) return fail(PX_EINVAL, "tap %d is not finite", k);
+    if (!std::isfinite(scale)) return fail(PX_EINVAL, "scale is not finite");
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (overlap(phi, grid_bytes(n, ld, dtype), out, flat_bytes(n, ld_out, dtype)))
+        return fail(PX_EALIAS, "out overlaps phi");
+    PX_HIP(stencil_launch(dtype, phi, n, ld, out, ld_out, taps, scale, bc, (hipStream_t)stream),
+           "stencil kernel launch");
+    return PX_OK;
+}
+
+int px_residual(const void *phi, int n, int ld, int dtype, const void *f, int ld_f, double h,
+                int bc, void *r, int ld_r, double *norms, px_ctx *ctx, void *stream)
+{
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = check_ptr(phi, dtype, "phi"))) return st;
+    if ((st = check_flat(f, n, ld_f, dtype, "f"))) return st;
+    if (r && (st = check_flat(r, n, ld_r, dtype, "r"))) return st;
+    if (!norms) return fail(PX_EINVAL, "norms is NULL");
+    if (reinterpret_cast<uintptr_t>(norms) % 8) return fail(PX_EINVAL, "norms is not 8-byte aligned");
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = check_pos(h, "h"))) return st;
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (r && (overlap(r, flat_bytes(n, ld_r, dtype), phi, grid_bytes(n, ld, dtype)) ||
+              overlap(r, flat_bytes(n, ld_r, dtype), f, flat_bytes(n, ld_f, dtype))))
+        return fail(PX_EALIAS, "r overlaps phi or f");
+    if ((st = set_device(ctx))) return st;
+    return residual_into(ctx, dtype, phi, n, ld, f, ld_f, h, bc, r, ld_r, norms, (hipStream_t)stream);
+}
+
+int px_jacobi_update(void *phi, int n, int ld, int dtype, const void *s, int ld_s, const void *f,
+                     int ld_f, double h, double lambda, void *stream)
+{
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = check_ptr(phi, dtype, "phi"))) return st;
+    if ((st = check_flat(s, n, ld_s, dtype, "s"))) return st;
+    if ((st = check_flat(f, n, ld_f, dtype, "f"))) return st;
+    if ((st = check_pos(h, "h")) || (st = check_pos(lambda, "lambda"))) return st;
+    if (overlap(phi, grid_bytes(n, ld, dtype), s, flat_bytes(n, ld_s, dtype)) ||
+        overlap(phi, grid_bytes(n, ld, dtype), f, flat_bytes(n, ld_f, dtype)))
+        return fail(PX_EALIAS, "phi overlaps s or f");
+    PX_HIP(jacobi_launch(dtype, phi, n, ld, s, ld_s, f, ld_f, lambda / (h * h), lambda,
+                         (hipStream_t)stream),
+           "jacobi kernel launch");
+    return PX_OK;
+}
+
+int px_relax_fused(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f,
+                   int ld_f, double h, double lambda, int nsweeps, int tblock, int bc, int resmode,
+                   double *norms, px_ctx *ctx, void *stream)
+{
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = check_ptr(phi_in, dtype, "phi_in")) || (st = check_ptr(phi_out, dtype, "phi_out")))
+        return st;
+    if ((st = check_flat(f, n, ld_f, dtype, "f"))) return st;
+    if ((st = check_pos(h, "h")) || (st = check_pos(lambda, "lambda"))) return st;
+    if (nsweeps < 0) return fail(PX_EINVAL, "nsweeps = %d < 0", nsweeps);
+    if (tblock < 0 || tblock > 8) return fail(PX_EINVAL, "tblock = %d outside [0, 8]", tblock);
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (resmode < RES_NONE || resmode > RES_FINAL) return fail(PX_EINVAL, "unknown resmode %d", resmode);
+    if (resmode != RES_NONE && !norms) return fail(PX_EINVAL, "norms is NULL");
+    if (norms && reinterpret_cast<uintptr_t>(norms) % 8) return fail(PX_EINVAL, "norms is not 8-byte aligned");
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    const size_t gb = grid_bytes(n, ld, dtype);
+    if (overlap(phi_in, gb, phi_out, gb)) return fail(PX_EALIAS, "phi_out overlaps phi_in");
+    if (overlap(f, flat_bytes(n, ld_f, dtype), phi_out, gb)) return fail(PX_EALIAS, "phi_out overlaps f");
+    if ((st = set_device(ctx))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (nsweeps == 0) {
+        PX_HIP(copy_grid_launch(dtype, phi_in, phi_out, n, ld, s), "copy kernel launch");
+        if (resmode != RES_NONE)
+            return residual_into(ctx, dtype, phi_in, n, ld, f, ld_f, h, bc, nullptr, 0, norms, s);
+        return PX_OK;
+    }
+    const int k = tblock ? tblock : default_tblock(dtype, n);
+    void *tmp = nullptr;
+    if ((nsweeps + k - 1) / k > 1) {
+        if ((st = ensure_grid(ctx, gb))) return st;
+        tmp = ctx->grid;
+    }
+    return run_sweeps(ctx, dtype, phi_in, phi_out, tmp, n, ld, f, ld_f, h, lambda, nsweeps, k, bc,
+                      resmode, norms, s);
+}
+
+int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, double h, double lambda,
+             const px_solve_opts *o, px_solve_stats *stats, px_ctx *ctx, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if (!o) return fail(PX_EINVAL, "opts is NULL");
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = check_ptr(phi, dtype, "phi"))) return st;
+    if ((st = check_flat(f, n, ld_f, dtype, "f"))) return st;
+    if ((st = check_pos(h, "h")) || (st = check_pos(lambda, "lambda"))) return st;
+    if (o->mode < PX_SOLVE_PLAIN || o->mode > PX_SOLVE_MIXED_BF16) return fail(PX_EINVAL, "unknown mode %d", o->mode);
+    if (o->mode != PX_SOLVE_PLAIN && dtype != F64)
+        return fail(PX_EINVAL, "mixed-precision modes need FP64 phi and f");
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(PX_EINVAL, "rtol must be finite and >= 0");
+    if (o->norm != 0 && o->norm != 1) return fail(PX_EINVAL, "norm must be 0 (max) or 1 (L2)");
+    if (o->max_sweeps < 0) return fail(PX_EINVAL, "max_sweeps < 0");
+    if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
+    if (!valid_bc(o->bc)) return fail(PX_EINVAL, "unknown bc %d", o->bc);
+    const int check_every = o->check_every > 0 ? o->check_every : 100;
+    const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : 32;
+    const size_t gb = grid_bytes(n, ld, dtype);
+    if (overlap(f, flat_bytes(n, ld_f, dtype), phi, gb)) return fail(PX_EALIAS, "phi overlaps f");
+    if ((st = set_device(ctx))) return st;
+    if ((st = ensure_norms(ctx))) return st;
+    if ((st = ensure_grid(ctx, gb))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    const int bc = o->bc;
+    const int k = o->tblock ? o->tblock : default_tblock(dtype, n);
+
+    auto read_norms = [&](double *dst) -> int {
+        PX_HIP(hipMemcpyAsync(ctx->norms_host, ctx->norms_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+               "norm readback");
+        PX_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        dst[0] = ctx->norms_host[0];
+        dst[1] = ctx->norms_host[1];
+        return PX_OK;
+    };
+    auto measure = [&](const double *nr) { return o->norm == 0 ? nr[0] : std::sqrt(nr[1]); };
+
+    // norms of f: the residual of the zero iterate is f itself
+    double fn[2];
+    {
+        // residual of zero: use the ctx grid, zeroed, as phi
+        PX_HIP(zero_grid_launch(dtype, ctx->grid, n, ld, s), "zero kernel launch");
+        if ((st = residual_into(ctx, dtype, ctx->grid, n, ld, f, ld_f, h, GHOST_FIXED, nullptr, 0,
+                                ctx->norms_dev, s)))
+            return st;
+        if ((st = read_norms(fn))) return st;
+    }
+    const double fref = measure(fn);
+    const double target = o->rtol * fref;
+
+    px_solve_stats S;
+    std::memset(&S, 0, sizeof S);
+    double nr[2] = {0, 0};
+    int result = PX_OK;
+    void *cur = phi;
+    void *oth = ctx->grid;
+
+    if (o->mode == PX_SOLVE_PLAIN) {
+        if ((st = residual_into(ctx, dtype, phi, n, ld, f, ld_f, h, bc, nullptr, 0, ctx->norms_dev, s)))
+            return st;
+        if ((st = read_norms(nr))) return st;
+        const double r0 = measure(nr);
+        for (;;) {
+            const double m = measure(nr);
+            if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) { result = fail(PX_ENONFINITE, "non-finite residual"); break; }
+            if (m <= target) break;
+            if (m > 1e8 * std::max(r0, fref)) { result = fail(PX_EDIVERGED, "residual grew from %g to %g", r0, m); break; }
+            if (S.sweeps >= o->max_sweeps) { result = fail(PX_ENOTCONV, "max_sweeps reached (rel res %g)", m / fref); break; }
+            const int todo = (int)std::min<int64_t>(check_every, o->max_sweeps - S.sweeps);
+            // one launch sequence cur -> oth; intermediate launches alternate through cur itself
+            // is not allowed (cur is the source), so run them as single-launch chunks of k.
+            int done = 0;
+            while (done < todo) {
+                const int ks = std::min(k, todo - done);
+                const bool last = done + ks == todo;
+                if ((st = run_sweeps(ctx, dtype, cur, oth, nullptr, n, ld, f, ld_f, h, lambda, ks, ks, bc,
+                                     last ? RES_FINAL : RES_NONE, ctx->norms_dev, s)))
+                    return st;
+                std::swap(cur, oth);
+                done += ks;
+            }
+            S.sweeps += todo;
+            S.outer_steps += 1;
+            if ((st = read_norms(nr))) return st;
+        }
+        if (cur != phi) PX_HIP(copy_grid_launch(dtype, cur, phi, n, ld, s), "copy kernel launch");
+    } else {
+        const int lowp = (o->mode == PX_SOLVE_MIXED_F32) ? F32 : BF16;
+        const int ldl = (n + 2 + 7) / 8 * 8;  // low-precision grids: rows padded to 16-byte multiples
+        const size_t lg = grid_bytes(n, ldl, lowp);
+        const size_t lr = flat_bytes(n, ldl, lowp);
+        // three ghosted low-precision grids (zero start, ping, pong) and r_low
+        const size_t gsz = (lg + 255) / 256 * 256;
+        const size_t off_r = 3 * gsz;
+        if ((st = ensure_mix(ctx, off_r + (lr + 255) / 256 * 256 + 256))) return st;
+        char *mb = static_cast<char *>(ctx->mix);
+        void *da = mb, *db = mb + gsz, *dc = mb + 2 * gsz;
+        // r_low sits one element past a 256-byte boundary, so (r_low - 1 element) is
+        // aligned and its rows line up with the ghosted grids' columns for vector loads
+        void *rl = mb + off_r + elem_size(lowp);
+        const int nblk = pointwise_num_blocks(n);
+        if ((st = ensure_partials(ctx, (size_t)nblk))) return st;
+        // step 0: oth = phi (copy with ghosts per bc), r = f - L phi
+        PX_HIP(refine_launch(lowp, (const double *)cur, nullptr, (double *)oth, n, ld, (const double *)f,
+                             ld_f, 1.0 / (h * h), bc, rl, ldl, partials(ctx), s),
+               "refine kernel launch");
+        PX_HIP(reduce_partials(partials(ctx), nblk, ctx->norms_dev, s), "norm reduction launch");
+        std::swap(cur, oth);
+        if ((st = read_norms(nr))) return st;
+        const double r0 = measure(nr);
+        for (;;) {
+            const double m = measure(nr);
+            if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) { result = fail(PX_ENONFINITE, "non-finite residual"); break; }
+            if (m <= target) break;
+            if (m > 1e8 * std::max(r0, fref)) { result = fail(PX_EDIVERGED, "residual grew from %g to %g", r0, m); break; }
+            if (S.sweeps >= o->max_sweeps) { result = fail(PX_ENOTCONV, "max_sweeps reached (rel res %g)", m / fref); break; }
+            // inner: delta = 0, `inner` low-precision sweeps on L delta = r_low
+            PX_HIP(zero_grid_launch(lowp, da, n, ldl, s), "zero kernel launch");
+            if ((st = run_sweeps(ctx, lowp, da, db, dc, n, ldl, rl, ldl, h, lambda, inner,
+                                 std::min(k, inner), bc, RES_NONE, nullptr, s)))
+                return st;
+            // outer: oth = cur + delta (FP64), r = f - L oth
+            PX_HIP(refine_launch(lowp, (const double *)cur, db, (double *)oth, n, ld, (const double *)f, ld_f,
+                                 1.0 / (h * h), bc, rl, ldl, partials(ctx), s),
+                   "refine kernel launch");
+            PX_HIP(reduce_partials(partials(ctx), nblk, ctx->norms_dev, s), "norm reduction launch");
+            std::swap(cur, oth);
+            S.sweeps += inner;
+            S.outer_steps += 1;
+            if ((st = read_norms(nr))) return st;
+        }
+        if (cur != phi) PX_HIP(copy_grid_launch(dtype, cur, phi, n, ld, s), "copy kernel launch");
+    }
+    PX_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    S.res_max = nr[0];
+    S.res_l2 = std::sqrt(nr[1]);
+    S.rel_res_max = fn[0] > 0 ? nr[0] / fn[0] : nr[0];
+    S.rel_res_l2 = fn[1] > 0 ? std::sqrt(nr[1] / fn[1]) : S.res_l2;
+    S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S;
+    return result;
+}
+
+}  // extern "C"

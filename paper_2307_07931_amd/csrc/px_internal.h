@@ -1,0 +1,104 @@
+// px_internal.h -- shared internals of the gfx950 HIP library (not part of the ABI).
+//
+// Element-type traits, the bfloat16 rounding used on every BF16 store, the
+// launcher descriptors the host API fills in, and the launcher prototypes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace px {
+
+enum Dtype { F64 = 0, F32 = 1, BF16 = 2 };
+enum Bc { DIRICHLET0 = 0, GHOST_FIXED = 1 };
+enum ResMode { RES_NONE = 0, RES_LAGGED = 1, RES_FINAL = 2 };
+
+struct bf16 {
+    uint16_t bits;
+};
+
+// Round-to-nearest-even of a binary32 to bfloat16 (quiet NaN kept NaN).
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// Storage traits: A is the arithmetic type, load/store convert, round() gives the
+// arithmetic value of what a store followed by a load would produce.
+template <typename T> struct Elem;
+template <> struct Elem<double> {
+    using A = double;
+    static constexpr int code = F64;
+    __device__ static A load(double x) { return x; }
+    __device__ static double store(A x) { return x; }
+    __device__ static A round(A x) { return x; }
+};
+template <> struct Elem<float> {
+    using A = float;
+    static constexpr int code = F32;
+    __device__ static A load(float x) { return x; }
+    __device__ static float store(A x) { return x; }
+    __device__ static A round(A x) { return x; }
+};
+template <> struct Elem<bf16> {
+    using A = float;
+    static constexpr int code = BF16;
+    __device__ static A load(bf16 x) { return bf16_to_f32(x.bits); }
+    __device__ static bf16 store(A x) { return bf16{f32_to_bf16_rne(x)}; }
+    __device__ static A round(A x) { return bf16_to_f32(f32_to_bf16_rne(x)); }
+};
+
+inline int elem_size(int dtype) { return dtype == F64 ? 8 : dtype == F32 ? 4 : 2; }
+
+// Per-wave (or per-block) partial norms: max|r| as the bit pattern of a
+// non-negative double (integer order == value order, NaN above +Inf) and the
+// sum of r^2.
+struct Partials {
+    unsigned long long *max_bits;
+    double *sum;
+};
+
+struct RelaxLaunch {
+    const void *in;
+    void *out;
+    const void *f;
+    int n, ld, ld_f;
+    double c, w, lam;  // 1/h^2, lambda/h^2, lambda (FP64; rounded once for FP32/BF16)
+    int bc;
+    int sweeps;        // sweeps in this launch (1..8)
+    int resmode;       // RES_NONE / RES_LAGGED / RES_FINAL for this launch
+    int rows;          // rows per wave tile
+    Partials part;     // needs >= relax_num_waves() entries when resmode != RES_NONE
+};
+
+// Number of wave tiles (== partial slots) a launch with these settings uses.
+int relax_num_waves(int dtype, int n, int sweeps, int resmode, int rows);
+// Default rows per tile for a given problem and sweeps per launch.
+int relax_default_rows(int dtype, int n, int sweeps);
+hipError_t relax_launch(int dtype, const RelaxLaunch &a, hipStream_t s);
+
+// Fixed-order reduction of `count` partials into norms[0] = max, norms[1] = sum.
+hipError_t reduce_partials(Partials p, int count, double *norms, hipStream_t s);
+int pointwise_num_blocks(int n);
+
+hipError_t stencil_launch(int dtype, const void *phi, int n, int ld, void *out, int ld_out,
+                          const double taps[9], double scale, int bc, hipStream_t s);
+hipError_t residual_launch(int dtype, const void *phi, int n, int ld, const void *f, int ld_f,
+                           double c, int bc, void *r, int ld_r, Partials part, hipStream_t s);
+hipError_t jacobi_launch(int dtype, void *phi, int n, int ld, const void *sv, int ld_s,
+                         const void *f, int ld_f, double w, double lam, hipStream_t s);
+hipError_t copy_grid_launch(int dtype, const void *in, void *out, int n, int ld, hipStream_t s);
+
+// Mixed-precision refinement pieces (FP64 outer step).
+// phi_out = phi_in + delta (interior; delta of dtype lowp, may be NULL for 0),
+// r = f - L phi_out written in FP64 partial norms and as lowp into r_low.
+hipError_t refine_launch(int lowp, const double *phi_in, const void *delta, double *phi_out,
+                         int n, int ld, const double *f, int ld_f, double c, int bc,
+                         void *r_low, int ld_r, Partials part, hipStream_t s);
+hipError_t zero_grid_launch(int dtype, void *p, int n, int ld, hipStream_t s);
+
+}  // namespace px

@@ -1,0 +1,156 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and
+rejects bad arguments on the host before any HIP call (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2307_07931_amd as px
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "protox.h")
+
+FAKE = 0x10000  # an aligned, never-dereferenced address: validation fails before use
+FAKE2 = 0x20000000
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(px_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = px.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for nm in names:
+        assert hasattr(L, nm), nm
+    assert set(px.EXPORTS) <= set(names)
+
+
+def test_version_and_empty_error():
+    assert "gfx950" in px.version()
+
+
+@pytest.fixture
+def ctx():
+    h = ctypes.c_void_p()
+    assert px.lib().px_ctx_create(0, ctypes.byref(h)) == px.OK  # allocates nothing
+    yield h
+    assert px.lib().px_ctx_destroy(h) == px.OK
+
+
+def relax(handle, **kw):
+    a = dict(phi_in=FAKE, phi_out=FAKE2, n=64, ld=66, dtype=px.F64, f=FAKE2 * 2, ld_f=64,
+             h=1 / 64, lam=1e-5, nsweeps=10, tblock=1, bc=0, resmode=2, norms=FAKE2 * 3, ctx=handle)
+    a.update(kw)
+    P = ctypes.c_void_p
+    return px.lib().px_relax_fused(P(a["phi_in"]), P(a["phi_out"]), a["n"], a["ld"], a["dtype"],
+                                   P(a["f"]), a["ld_f"], a["h"], a["lam"], a["nsweeps"], a["tblock"],
+                                   a["bc"], a["resmode"], P(a["norms"]), a["ctx"], None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), px.EINVAL),
+    (dict(n=-3), px.EINVAL),
+    (dict(ld=65), px.EINVAL),
+    (dict(ld_f=63), px.EINVAL),
+    (dict(phi_in=0), px.EINVAL),
+    (dict(phi_out=0), px.EINVAL),
+    (dict(f=0), px.EINVAL),
+    (dict(phi_in=FAKE + 4), px.EINVAL),       # misaligned for FP64
+    (dict(dtype=7), px.EINVAL),
+    (dict(bc=5), px.EINVAL),
+    (dict(resmode=3), px.EINVAL),
+    (dict(norms=0), px.EINVAL),
+    (dict(norms=FAKE2 * 3 + 4), px.EINVAL),
+    (dict(h=0.0), px.EINVAL),
+    (dict(h=float("nan")), px.EINVAL),
+    (dict(lam=-1.0), px.EINVAL),
+    (dict(lam=float("inf")), px.EINVAL),
+    (dict(nsweeps=-1), px.EINVAL),
+    (dict(tblock=9), px.EINVAL),
+    (dict(tblock=-1), px.EINVAL),
+    (dict(ctx=None), px.EINVAL),
+    (dict(phi_out=FAKE + 8 * 100), px.EALIAS),  # overlaps phi_in
+    (dict(f=FAKE2 + 8 * 66), px.EALIAS),        # overlaps phi_out
+])
+def test_relax_validation(ctx, kw, code):
+    assert relax(ctx, **kw) == code
+    assert px.last_error() != ""
+
+
+def test_relax_bf16_alignment_is_two_bytes(ctx):
+    # 2-byte alignment is enough for BF16; odd address is not
+    assert relax(ctx, dtype=px.BF16, phi_in=FAKE + 1) == px.EINVAL
+
+
+def test_stencil_validation():
+    P = ctypes.c_void_p
+    t = (ctypes.c_double * 9)(*px.LAPLACE_TAPS)
+    L = px.lib()
+    assert L.px_apply_stencil(P(FAKE), 8, 10, 0, P(FAKE2), 8, None, 1.0, 0, None) == px.EINVAL
+    assert L.px_apply_stencil(P(FAKE), 8, 9, 0, P(FAKE2), 8, t, 1.0, 0, None) == px.EINVAL
+    assert L.px_apply_stencil(P(FAKE), 8, 10, 0, P(FAKE + 80), 8, t, 1.0, 0, None) == px.EALIAS
+    bad = (ctypes.c_double * 9)(*([float("nan")] + [0.0] * 8))
+    assert L.px_apply_stencil(P(FAKE), 8, 10, 0, P(FAKE2), 8, bad, 1.0, 0, None) == px.EINVAL
+    assert L.px_apply_stencil(P(FAKE), 8, 10, 0, P(FAKE2), 8, t, float("inf"), 0, None) == px.EINVAL
+
+
+def test_residual_and_jacobi_validation(ctx):
+    P = ctypes.c_void_p
+    L = px.lib()
+    assert L.px_residual(P(FAKE), 8, 10, 0, P(FAKE2), 8, 0.125, 0, None, 0, None, ctx, None) == px.EINVAL
+    assert L.px_residual(P(FAKE), 8, 10, 0, P(FAKE2), 8, 0.125, 0, None, 0, P(FAKE2 * 2), None,
+                         None) == px.EINVAL
+    assert L.px_residual(P(FAKE), 8, 10, 0, P(FAKE2), 8, 0.125, 0, P(FAKE2 + 8), 8, P(FAKE2 * 2),
+                         ctx, None) == px.EALIAS
+    assert L.px_jacobi_update(P(FAKE), 8, 10, 0, P(FAKE2), 8, P(FAKE2 * 2), 8, 0.125, 0.0,
+                              None) == px.EINVAL
+    assert L.px_jacobi_update(P(FAKE), 8, 10, 0, P(FAKE + 16), 8, P(FAKE2 * 2), 8, 0.125, 1e-3,
+                              None) == px.EALIAS
+
+
+def test_solve_validation(ctx):
+    P = ctypes.c_void_p
+    L = px.lib()
+    st = px._SolveStats()
+
+    def solve(dtype=0, **kw):
+        o = px._SolveOpts(kw.get("mode", 0), kw.get("norm", 0), kw.get("rtol", 1e-8),
+                          kw.get("max_sweeps", 100), 10, 8, kw.get("tblock", 0), kw.get("bc", 0))
+        return L.px_solve(P(FAKE), 8, 10, dtype, P(FAKE2), 8, 0.125, 1e-3, ctypes.byref(o),
+                          ctypes.byref(st), ctx, None)
+
+    assert solve(mode=9) == px.EINVAL
+    assert solve(mode=px.SOLVE_MIXED_F32, dtype=px.F32) == px.EINVAL
+    assert solve(rtol=-1.0) == px.EINVAL
+    assert solve(norm=2) == px.EINVAL
+    assert solve(max_sweeps=-5) == px.EINVAL
+    assert solve(tblock=12) == px.EINVAL
+    assert solve(bc=3) == px.EINVAL
+    assert L.px_solve(P(FAKE), 8, 10, 0, P(FAKE2), 8, 0.125, 1e-3, None, ctypes.byref(st), ctx,
+                      None) == px.EINVAL
+
+
+def test_ctx_validation():
+    L = px.lib()
+    h = ctypes.c_void_p()
+    assert L.px_ctx_create(-1, ctypes.byref(h)) == px.EINVAL
+    assert L.px_ctx_create(0, None) == px.EINVAL
+    assert L.px_ctx_destroy(None) == px.OK
+    assert L.px_ctx_set_tile_rows(None, 4) == px.EINVAL
+    assert L.px_ctx_reserve(None, 8, 10, 0) == px.EINVAL
+
+
+def test_python_binding_rejects_bad_layouts():
+    torch = pytest.importorskip("torch")
+    phi = torch.zeros(10, 10, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        px._ld(phi.t(), 10, 10, "phi")  # not unit column stride
+    with pytest.raises(ValueError):
+        px._ld(phi, 9, 10, "phi")
+    with pytest.raises(TypeError):
+        px.dtype_code(torch.zeros(1, dtype=torch.int32))

@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bar: bit-exact for every element of phi (interior and edge ghosts) in FP64,
+FP32 and BF16, and for max|r|; sum r^2 within 1e-12 relative (it is summed in
+a different order on the two sides)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2307_07931_amd as px
+import workloads as W
+from oracle import exact
+
+import helpers as H
+
+pytestmark = pytest.mark.gpu
+OMEGA = 2.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    H.require_gpu()
+    c = px.Context()
+    yield c
+    c.close()
+
+
+def params(n, node_centred=False):
+    h = 1.0 / (n + 1) if node_centred else 1.0 / n
+    return h, OMEGA * h * h / 4.0
+
+
+# --------------------------------------------------- manufactured 64 x 64 --
+
+@pytest.mark.parametrize("tblock", range(1, 9))
+def test_manufactured_64_fp64_matches_oracle_and_closed_form(ctx, tblock):
+    n, N = 64, 100
+    h, lam = params(n)
+    f = W.manufactured_rhs(n)
+    phi0 = np.zeros((n + 2, n + 2))
+    print(f"case: manufactured n={n} sweeps={N} tblock={tblock}", flush=True)
+    g, norms = H.gpu_relax(phi0, f, n, h, lam, N, "f64", ctx, tblock=tblock)
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, N, "f64")
+    H.assert_grid_bitwise(g, ref, n)
+    H.assert_norms(norms, mx, sq)
+    cf = exact.manufactured_closed_form(n, N, OMEGA)
+    assert norms[0] == pytest.approx(cf["res_max_final"], rel=1e-12)
+    err = np.abs(g[1:n + 1, 1:n + 1] - W.manufactured_solution(n)).max()
+    assert err == pytest.approx(cf["err_max"], rel=1e-12)
+
+
+# ------------------------------------------------------- general parity --
+
+CASES = [
+    # dt, n, nsweeps, tblock, bc, resmode
+    ("f64", 1, 3, 1, 0, 2), ("f64", 2, 5, 2, 0, 1), ("f64", 3, 7, 3, 1, 2),
+    ("f64", 7, 9, 8, 0, 2), ("f64", 64, 13, 4, 0, 1), ("f64", 125, 11, 5, 0, 2),
+    ("f64", 130, 16, 8, 1, 2), ("f64", 257, 9, 1, 0, 2), ("f64", 300, 12, 6, 1, 1),
+    ("f64", 97, 0, 4, 0, 2), ("f64", 40, 17, 7, 0, 0),
+    ("f32", 1, 4, 4, 0, 2), ("f32", 5, 6, 2, 1, 1), ("f32", 64, 10, 1, 0, 2),
+    ("f32", 129, 12, 3, 0, 2), ("f32", 255, 16, 8, 1, 2), ("f32", 300, 9, 4, 0, 1),
+    ("bf16", 3, 5, 5, 0, 2), ("bf16", 33, 8, 2, 1, 2), ("bf16", 130, 12, 4, 0, 1),
+    ("bf16", 261, 16, 8, 0, 2),
+]
+
+
+@pytest.mark.parametrize("dt,n,nsweeps,tblock,bc,resmode", CASES)
+def test_relax_matches_oracle(ctx, dt, n, nsweeps, tblock, bc, resmode):
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 1000 + n)
+    phi0 = W.uniform_phi(n, 2000 + n)
+    print(f"case: {dt} n={n} sweeps={nsweeps} tblock={tblock} bc={bc} res={resmode}", flush=True)
+    g, norms = H.gpu_relax(phi0, f, n, h, lam, nsweeps, dt, ctx, tblock=tblock, bc=bc,
+                           resmode=resmode)
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, nsweeps, dt, bc=bc, resmode=resmode)
+    H.assert_grid_bitwise(g, ref, n)
+    if resmode != px.RES_NONE:
+        H.assert_norms(norms, mx, sq)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_all_tblocks_and_tile_shapes_agree(ctx, dt):
+    """k sweeps per launch and the tile height change nothing, bit for bit."""
+    n, N = 203, 24
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 5)
+    phi0 = W.uniform_phi(n, 6)
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, N, dt)
+    for rows in (0, 1, 3, 17, 300):
+        ctx.set_tile_rows(rows)
+        for tb in range(1, 9):
+            print(f"case: {dt} rows={rows} tblock={tb}", flush=True)
+            g, norms = H.gpu_relax(phi0, f, n, h, lam, N, dt, ctx, tblock=tb)
+            H.assert_grid_bitwise(g, ref, n, what=f"rows={rows} tblock={tb}")
+            H.assert_norms(norms, mx, sq)
+    ctx.set_tile_rows(0)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_unaligned_layouts(ctx, dt):
+    """ld = n+2 (rows not 16-byte aligned for FP32/BF16) and f packed n wide with no
+    alignment help: the scalar paths give the same bits."""
+    n, N = 131, 10
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 7)
+    phi0 = W.uniform_phi(n, 8)
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, N, dt)
+    for ld, ld_f, fal in ((n + 2, n, False), (n + 3, n + 1, False), (None, None, True), (n + 2, None, True)):
+        print(f"case: {dt} ld={ld} ld_f={ld_f} f_aligned={fal}", flush=True)
+        g, norms = H.gpu_relax(phi0, f, n, h, lam, N, dt, ctx, tblock=3, ld=ld, ld_f=ld_f, f_aligned=fal)
+        H.assert_grid_bitwise(g, ref, n, what=f"ld={ld} ld_f={ld_f}")
+        H.assert_norms(norms, mx, sq)
+
+
+def test_node_centred_ghost_fixed_closed_form(ctx):
+    n, N = 64, 100
+    h, lam = params(n, node_centred=True)
+    f = -2 * np.pi ** 2 * W.sine_mode(n, 1, 1, node_centred=True)
+    g, norms = H.gpu_relax(np.zeros((n + 2, n + 2)), f, n, h, lam, N, "f64", ctx, tblock=4, bc=1)
+    cf = exact.manufactured_closed_form(n, N, OMEGA, node_centred=True)
+    np.testing.assert_allclose(g[1:n + 1, 1:n + 1], cf["phi"], rtol=0, atol=5e-15)
+    assert norms[0] == pytest.approx(cf["res_max_final"], rel=1e-12)
+
+
+# ----------------------------------------------------- invariants on GPU --
+
+def test_split_run_is_bitwise(ctx):
+    n = 260
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 9)
+    phi0 = W.uniform_phi(n, 10)
+    a, _ = H.gpu_relax(phi0, f, n, h, lam, 40, "f64", ctx, tblock=4)
+    b, _ = H.gpu_relax(phi0, f, n, h, lam, 17, "f64", ctx, tblock=8)
+    b, _ = H.gpu_relax(b[:, :n + 2], f, n, h, lam, 23, "f64", ctx, tblock=3)
+    H.assert_grid_bitwise(a, b, n)
+
+
+def test_lagged_equals_final_of_previous(ctx):
+    n = 150
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 11)
+    phi0 = np.zeros((n + 2, n + 2))
+    _, nl = H.gpu_relax(phi0, f, n, h, lam, 21, "f64", ctx, tblock=4, resmode=px.RES_LAGGED)
+    _, nf = H.gpu_relax(phi0, f, n, h, lam, 20, "f64", ctx, tblock=4, resmode=px.RES_FINAL)
+    assert nl[0] == nf[0]
+    assert nl[1] == pytest.approx(nf[1], rel=1e-13)
+
+
+def test_nan_in_rhs_propagates_to_max_norm(ctx):
+    n = 70
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 12)
+    f[30, 40] = np.nan
+    _, norms = H.gpu_relax(np.zeros((n + 2, n + 2)), f, n, h, lam, 6, "f64", ctx, tblock=2)
+    assert np.isnan(norms[0]) and np.isnan(norms[1])
+
+
+# ------------------------------------------ stencil / residual / unfused --
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_apply_stencil_quadratic_exact(ctx, dt):
+    n = 16 if dt == "bf16" else 200
+    phi = W.quadratic_grid(n, 1, 0, 1, 0, 0, 0, shift=n // 2 + 1)
+    pd = H.device_grid(phi, n, dt)
+    out = torch.full((n, n + 5), 3.0, dtype=H.TORCH_DTYPE[dt], device="cuda")
+    px.apply_stencil(pd, n, out, bc=px.BC_GHOST_FIXED)
+    torch.cuda.synchronize()
+    assert torch.all(out[:, :n].float() == 4.0)
+    assert torch.all(out[:, n:].float() == 3.0)  # padding untouched
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("taps,scale,bc", [
+    (px.LAPLACE_TAPS, 1.0, 0), (px.LAPLACE_TAPS, 4096.0, 1),
+    ((1, 0, -1, 0, 0, 0, -1, 0, 1), 0.25, 0), ((0.5, 1, 0.25, 2, -3, 1, 0.125, -1, 0.75), 1.5, 0),
+    ((0.5, 1, 0.25, 2, -3, 1, 0.125, -1, 0.75), 1.0, 1),
+])
+def test_apply_stencil_matches_oracle(ctx, dt, taps, scale, bc):
+    n = 77
+    phi = W.uniform_phi(n, 13)
+    pd = H.device_grid(phi, n, dt)
+    out = torch.zeros((n, n), dtype=H.TORCH_DTYPE[dt], device="cuda")
+    px.apply_stencil(pd, n, out, taps=taps, scale=scale, bc=bc)
+    torch.cuda.synchronize()
+    ref = oracle.apply_stencil(H.oracle_input(phi, dt), n, taps=taps, scale=scale, bc=bc)
+    assert np.array_equal(H.bits(H.to_storage_np(out, dt)), H.bits(ref))
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_residual_matches_oracle(ctx, dt, bc):
+    n = 123
+    h, _ = params(n)
+    phi = W.uniform_phi(n, 14)
+    f = W.uniform_rhs(n, 15)
+    pd = H.device_grid(phi, n, dt)
+    fd = H.device_rhs(f, n, dt)
+    r = torch.zeros((n, n), dtype=H.TORCH_DTYPE[dt], device="cuda")
+    norms = torch.zeros(2, dtype=torch.float64, device="cuda")
+    px.residual(pd, n, fd, h, norms, ctx, bc=bc, r=r)
+    torch.cuda.synchronize()
+    rr, mx, sq = oracle.residual(H.oracle_input(phi, dt), H.oracle_input(f, dt), n, h, bc=bc)
+    assert np.array_equal(H.bits(H.to_storage_np(r, dt)), H.bits(rr))
+    H.assert_norms(norms.cpu().numpy(), mx, sq)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_unfused_sweep_equals_fused(ctx, dt):
+    """Proto-shaped sweep (stencil into a temporary, pointwise update in place, residual
+    of the new iterate) gives the fused kernel's bits.  (In BF16 the temporary itself is
+    stored in BF16, so the unfused form rounds once more by construction.)"""
+    n, N = 190, 7
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 16)
+    phi0 = W.uniform_phi(n, 17)
+    pd = H.device_grid(phi0, n, dt)
+    fd = H.device_rhs(f, n, dt)
+    tmp = torch.zeros((n, n), dtype=H.TORCH_DTYPE[dt], device="cuda")
+    norms = torch.zeros(2, dtype=torch.float64, device="cuda")
+    for _ in range(N):
+        px.apply_stencil(pd, n, tmp)
+        px.jacobi_update(pd, n, tmp, fd, h, lam)
+    px.residual(pd, n, fd, h, norms, ctx)
+    torch.cuda.synchronize()
+    g, nf = H.gpu_relax(phi0, f, n, h, lam, N, dt, ctx, tblock=4)
+    un = H.to_storage_np(pd, dt)
+    inner = np.zeros((n + 2, n + 2), dtype=bool)
+    inner[1:n + 1, 1:n + 1] = True  # the in-place update leaves ghosts alone
+    H.assert_grid_bitwise(un, g, n, mask=inner)
+    assert float(norms[0]) == nf[0]

@@ -312,3 +312,25 @@ def test_refinement_reaches_fp64_accuracy(lowp, k_in):
     g = exact.mode_factor(n, 1, 1, OMEGA)
     plain = np.log(1e-12) / np.log(g)
     assert steps * k_in <= 1.25 * plain + 2 * k_in, (steps * k_in, plain)
+
+
+# ------------------------------------------------- box interfaces (windows) --
+
+def test_window_with_fixed_interface_ghosts_matches_full_grid():
+    """A sub-box whose interface ghost layers are held at their initial values reproduces
+    the full-grid sweeps exactly on every cell at least N cells from those interfaces
+    (information travels one cell per sweep), and not one cell closer."""
+    import helpers
+    n, N, B = 48, 9, 30
+    h, lam = lam_of(n)
+    f = W.uniform_rhs(n, 41)
+    phi0 = W.uniform_phi(n, 42)
+    full, _, _ = oracle.relax(phi0, f, n, h, lam, N, resmode=oracle.RES_NONE)
+    for r0, c0 in ((1, 1), (n - B + 1, 1), (10, 12), (n - B + 1, n - B + 1)):
+        assert helpers.window_check(full, phi0, f, n, h, lam, N, r0, c0, B, "f64") > 0
+    # one row closer to a fixed interface the window result is no longer exact
+    pw = np.ascontiguousarray(phi0[9:9 + B + 2, 11:11 + B + 2])
+    fw = np.ascontiguousarray(f[9:9 + B, 11:11 + B])
+    F = oracle.BC_GHOST_FIXED
+    out, _, _ = oracle.relax_sides(pw, fw, B, h, lam, N, (F, F, F, F), resmode=oracle.RES_NONE)
+    assert np.any(out[N - 1, N:B + 2 - N] != full[9 + N - 1, 11 + N:11 + B + 2 - N])
