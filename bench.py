@@ -31,7 +31,7 @@ N = 4096
 SWEEPS = 200
 OMEGA = 2.0 / 3.0
 # launch configuration timed by default (also the full-size parity tests' configuration)
-BENCH_TBLOCK = {"f64": 4, "f32": 4}
+BENCH_TBLOCK = {"f64": 8, "f32": 8}
 BYTES_PER_CELL = {"f64": 24, "f32": 12, "bf16": 6}  # read phi + f, write phi', per launch
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 

@@ -149,13 +149,11 @@ def alloc_grid(n: int, dtype=torch.float64, device="cuda", ld: int | None = None
 
 
 def alloc_rhs(n: int, dtype=torch.float64, device="cuda", ld_f: int | None = None) -> torch.Tensor:
-    """Zeroed n x ld_f right-hand side placed one element past a 256-byte boundary,
-    so that its columns line up with a grid's interior columns for vector loads."""
+    """Zeroed n x ld_f right-hand side; default ld_f = n rounded up to 128 bytes (rows
+    16-byte aligned, so the relaxation kernels use vector loads)."""
     es = torch.empty(0, dtype=dtype).element_size()
-    ld_f = ld_f or round_up(n + 2, 128 // es)
-    pad = 256 // es
-    base = torch.zeros(n * ld_f + pad, dtype=dtype, device=device)
-    return base[1:1 + n * ld_f].view(n, ld_f)
+    ld_f = ld_f or round_up(n, 128 // es)
+    return torch.zeros((n, ld_f), dtype=dtype, device=device)
 
 
 # ----------------------------------------------------------------- context --

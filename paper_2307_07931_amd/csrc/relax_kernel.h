@@ -1,0 +1,547 @@
+// relax_kernel.h -- fused, temporally blocked damped-Jacobi relaxation for gfx950.
+//
+// One kernel launch performs K sweeps (Section IV, Eq. 3 in the OL form
+// phi' = (phi + w s) - lambda f with s the 5-point stencil of Eq. 1) and,
+// on request, the max-norm of the residual (the OL norm expression), reading
+// phi and f from HBM once and writing phi' once.
+//
+// Work decomposition ("2.5D" streaming, one wavefront = one tile):
+//   * a wave owns 64*V consecutive columns (V elements per lane, 16 bytes for
+//     FP64, 8 bytes for FP32/BF16 ... see VecOf) and a band of `rows` rows;
+//   * it streams down its band one input row per step; level t (t = 1..K) of
+//     the time pipeline is computed one row behind level t-1, from a 3-row
+//     register window of level t-1, so all K sweeps happen in registers;
+//   * east/west neighbours come from the adjacent lane with a cross-lane
+//     shift, so no LDS and no barriers are needed -- waves are independent;
+//   * the wave recomputes a halo of NL columns on each side and NL rows above
+//     and below its band (overlapped tiling), so a tile's output depends only
+//     on what the tile itself loaded.  Output columns per wave: `stride`.
+// Boundary: DIRICHLET0 replaces the neighbour across the boundary face by
+// -(centre) at every level (odd reflection applied on the fly); GHOST_FIXED
+// keeps ghost cells as fixed points of every level.
+// Results are bit-identical to one sweep at a time: every level rounds to the
+// storage type exactly as a store would, and the arithmetic order is fixed:
+// s = ((((N - 4C) + W) + E) + S), phi' = (C + w s) - lambda f, r = f - c s.
+//
+// Partial norms are written per wave (max|r| as bit pattern, sum r^2 in a
+// fixed lane/row order) and reduced in fixed order by reduce_partials().
+#pragma once
+#include "px_internal.h"
+
+#include <algorithm>
+
+namespace px {
+namespace relax_detail {
+
+constexpr int WAVE = 64;
+constexpr int WAVES_PER_BLOCK = 4;
+#ifndef PX_PREFETCH
+#define PX_PREFETCH 2
+#endif
+constexpr int PREFETCH = PX_PREFETCH;  // input rows in flight ahead of the row being consumed
+
+template <typename T> struct VecOf;
+template <> struct VecOf<double> { static constexpr int V = 2; };
+template <> struct VecOf<float> { static constexpr int V = 4; };
+template <> struct VecOf<bf16> { static constexpr int V = 4; };
+
+inline int vec_of(int dtype) { return dtype == F64 ? 2 : 4; }
+
+struct Geometry {
+    int halo, col_origin, stride, tiles_x, tiles_y, rows, ntiles;
+};
+
+// Column partition: a wave loads 64*V columns starting `halo` columns left of its
+// output columns [col_origin + tx*stride, ... + stride).  halo >= NL (the columns
+// each level invalidates at the wave's edges), rounded up to V so that loads and
+// the output partition are both V-aligned.
+inline Geometry make_geometry(int V, int n, int NL, int rows)
+{
+    Geometry g;
+    g.halo = (NL + V - 1) / V * V;
+    g.col_origin = 0;
+    g.stride = WAVE * V - 2 * g.halo;
+    g.tiles_x = (n + 2 + g.stride - 1) / g.stride;
+    g.rows = rows;
+    g.tiles_y = (n + 2 + rows - 1) / rows;
+    g.ntiles = g.tiles_x * g.tiles_y;
+    return g;
+}
+
+struct KArgs {
+    const void *in;
+    void *out;
+    const void *f;
+    int n, ld, ld_f, bc;
+    double c, w, lam;
+    int halo, col_origin, stride, tiles_x, rows, ntiles;
+    unsigned long long *pmax;
+    double *psum;
+};
+
+// --- cross-lane shifts through DPP (a VALU operand modifier, no LDS traffic):
+// wave_shr:1 gives lane l the value of lane l-1, wave_shl:1 that of lane l+1.
+// Lanes at the ends of the wave receive 0; their columns are halo columns whose
+// values are never used for an output.
+constexpr int DPP_WAVE_SHR1 = 0x138;
+constexpr int DPP_WAVE_SHL1 = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_shift(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_shift(double x)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <typename A> __device__ __forceinline__ A lane_from_left(A x) { return dpp_shift<DPP_WAVE_SHR1>(x); }
+template <typename A> __device__ __forceinline__ A lane_from_right(A x) { return dpp_shift<DPP_WAVE_SHL1>(x); }
+
+// --- memory access through buffer instructions.  A descriptor covers one row
+// (wave-uniform, built with scalar instructions); the hardware returns 0 for
+// loads and drops stores whose byte offset lies outside it, so a row outside the
+// array gets a zero-sized descriptor and a masked lane gets the offset OOB.  No
+// branches around loads: rows prefetched ahead stay in flight.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, gfx9-family data format
+constexpr int OOB = (int)0x80000000u;    // beyond every row descriptor (rows < 2 GiB)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int row, int nrows,
+                                                           int row_bytes)
+{
+    const bool ok = row >= 0 && row < nrows;
+    const char *p = static_cast<const char *>(base) + (size_t)(ok ? row : 0) * (size_t)row_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, ok ? row_bytes : 0,
+                                             RSRC_WORD3);
+}
+
+// Raw load / store of V consecutive elements, as one vector access (VEC) or V
+// scalar accesses.  Raw<T,V,VEC> holds the loaded bits until they are consumed.
+template <typename T, int V, bool VEC> struct Io;
+
+template <int V> struct Io<double, V, true> {
+    static_assert(V == 2, "FP64 vector access is 16 bytes");
+    using A = double;
+    struct Raw { u32x4 u; };
+    __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
+    {
+        return Raw{__builtin_amdgcn_raw_buffer_load_b128(r, col0 * 8, 0, 0)};
+    }
+    __device__ static void unpack(const Raw &x, A (&d)[V])
+    {
+        d[0] = __hiloint2double((int)x.u.y, (int)x.u.x);
+        d[1] = __hiloint2double((int)x.u.w, (int)x.u.z);
+    }
+    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V])
+    {
+        u32x4 u;
+        u.x = (unsigned)__double2loint(d[0]);
+        u.y = (unsigned)__double2hiint(d[0]);
+        u.z = (unsigned)__double2loint(d[1]);
+        u.w = (unsigned)__double2hiint(d[1]);
+        __builtin_amdgcn_raw_buffer_store_b128(u, r, off_elems == OOB ? OOB : off_elems * 8, 0, 0);
+    }
+};
+template <int V> struct Io<double, V, false> {
+    using A = double;
+    struct Raw { u32x2 u[V]; };
+    __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
+    {
+        Raw x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b64(r, (col0 + v) * 8, 0, 0);
+        return x;
+    }
+    __device__ static void unpack(const Raw &x, A (&d)[V])
+    {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = __hiloint2double((int)x.u[v].y, (int)x.u[v].x);
+    }
+};
+template <int V> struct Io<float, V, true> {
+    static_assert(V == 4, "FP32 vector access is 16 bytes");
+    using A = float;
+    struct Raw { u32x4 u; };
+    __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
+    {
+        return Raw{__builtin_amdgcn_raw_buffer_load_b128(r, col0 * 4, 0, 0)};
+    }
+    __device__ static void unpack(const Raw &x, A (&d)[V])
+    {
+        d[0] = __uint_as_float(x.u.x);
+        d[1] = __uint_as_float(x.u.y);
+        d[2] = __uint_as_float(x.u.z);
+        d[3] = __uint_as_float(x.u.w);
+    }
+    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V])
+    {
+        u32x4 u;
+        u.x = __float_as_uint(d[0]);
+        u.y = __float_as_uint(d[1]);
+        u.z = __float_as_uint(d[2]);
+        u.w = __float_as_uint(d[3]);
+        __builtin_amdgcn_raw_buffer_store_b128(u, r, off_elems == OOB ? OOB : off_elems * 4, 0, 0);
+    }
+};
+template <int V> struct Io<float, V, false> {
+    using A = float;
+    struct Raw { unsigned u[V]; };
+    __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
+    {
+        Raw x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b32(r, (col0 + v) * 4, 0, 0);
+        return x;
+    }
+    __device__ static void unpack(const Raw &x, A (&d)[V])
+    {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = __uint_as_float(x.u[v]);
+    }
+};
+template <int V> struct Io<bf16, V, true> {
+    static_assert(V == 4, "BF16 vector access is 8 bytes");
+    using A = float;
+    struct Raw { u32x2 u; };
+    __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
+    {
+        return Raw{__builtin_amdgcn_raw_buffer_load_b64(r, col0 * 2, 0, 0)};
+    }
+    __device__ static void unpack(const Raw &x, A (&d)[V])
+    {
+        d[0] = __uint_as_float(x.u.x << 16);
+        d[1] = __uint_as_float(x.u.x & 0xffff0000u);
+        d[2] = __uint_as_float(x.u.y << 16);
+        d[3] = __uint_as_float(x.u.y & 0xffff0000u);
+    }
+    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V])
+    {
+        u32x2 u;
+        u.x = (unsigned)f32_to_bf16_rne(d[0]) | ((unsigned)f32_to_bf16_rne(d[1]) << 16);
+        u.y = (unsigned)f32_to_bf16_rne(d[2]) | ((unsigned)f32_to_bf16_rne(d[3]) << 16);
+        __builtin_amdgcn_raw_buffer_store_b64(u, r, off_elems == OOB ? OOB : off_elems * 2, 0, 0);
+    }
+};
+template <int V> struct Io<bf16, V, false> {
+    using A = float;
+    struct Raw { unsigned short u[V]; };
+    __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
+    {
+        Raw x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b16(r, (col0 + v) * 2, 0, 0);
+        return x;
+    }
+    __device__ static void unpack(const Raw &x, A (&d)[V])
+    {
+#pragma unroll
+        for (int v = 0; v < V; ++v) d[v] = __uint_as_float((unsigned)x.u[v] << 16);
+    }
+};
+
+// Single-element masked store (edge tiles, ghost cells).
+__device__ __forceinline__ void store1(__amdgpu_buffer_rsrc_t r, int col, bool ok, double x)
+{
+    u32x2 u;
+    u.x = (unsigned)__double2loint(x);
+    u.y = (unsigned)__double2hiint(x);
+    __builtin_amdgcn_raw_buffer_store_b64(u, r, ok ? col * 8 : OOB, 0, 0);
+}
+__device__ __forceinline__ void store1_f(__amdgpu_buffer_rsrc_t r, int col, bool ok, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, ok ? col * 4 : OOB, 0, 0);
+}
+__device__ __forceinline__ void store1_b(__amdgpu_buffer_rsrc_t r, int col, bool ok, float x)
+{
+    __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_rne(x), r, ok ? col * 2 : OOB, 0, 0);
+}
+template <typename T> struct Store1;
+template <> struct Store1<double> {
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, int c, bool ok, double x) { store1(r, c, ok, x); }
+};
+template <> struct Store1<float> {
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, int c, bool ok, float x) { store1_f(r, c, ok, x); }
+};
+template <> struct Store1<bf16> {
+    __device__ static void st(__amdgpu_buffer_rsrc_t r, int c, bool ok, float x) { store1_b(r, c, ok, x); }
+};
+
+// Stores the elements of V consecutive columns col0.. that fall in [lo, hi),
+// negated if asked.  Whole vectors when the tile is known to hold only whole
+// vectors (`whole`, wave-uniform), element by element otherwise.
+template <typename T, int V, bool VEC>
+__device__ __forceinline__ void store_cols(__amdgpu_buffer_rsrc_t r, int col0, int lo, int hi,
+                                           bool whole, const typename Elem<T>::A (&val)[V], bool negate)
+{
+    using A = typename Elem<T>::A;
+    A x[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) x[v] = negate ? -val[v] : val[v];
+    if constexpr (VEC) {
+        if (whole) {
+            Io<T, V, true>::store(r, (col0 >= lo && col0 + V <= hi) ? col0 : OOB, x);
+            return;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) Store1<T>::st(r, col0 + v, col0 + v >= lo && col0 + v < hi, x[v]);
+}
+
+template <typename T, int V, int K, int RM, int PF, bool VEC>
+__global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const KArgs p)
+{
+    using E = Elem<T>;
+    using A = typename E::A;
+    using IO = Io<T, V, VEC>;
+    using Raw = typename IO::Raw;
+    constexpr int NL = K + (RM == RES_FINAL ? 1 : 0);  // pipeline levels
+    constexpr int RL = (RM == RES_FINAL) ? K + 1 : K;  // level that takes the residual
+    constexpr int FQ = RL + 1;                         // f rows kept in registers
+    constexpr int ES = (int)sizeof(T);
+
+    // XCD-aware block order: block b runs on XCD b % 8; give each XCD a contiguous
+    // run of tiles so neighbouring tiles (shared halo rows/columns) share an L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int nb8 = nb & ~7;
+    const int lb = (b < nb8) ? ((b & 7) * (nb8 >> 3) + (b >> 3)) : b;
+    // the wave index is uniform across the wave; say so, so every tile quantity and
+    // every row descriptor lives in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int tile = lb * WAVES_PER_BLOCK + wave;
+    if (tile >= p.ntiles) return;  // wave-uniform; waves never synchronise
+    const int lane = threadIdx.x & (WAVE - 1);
+
+    const int n = p.n;
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int oc0 = p.col_origin + tx * p.stride;  // output columns [oc0, oc1)
+    const int oc1 = min(oc0 + p.stride, n + 2);
+    const int mc = oc0 - p.halo + lane * V;        // first column held by this lane
+    const int y0 = ty * p.rows, y1 = min(y0 + p.rows, n + 2);
+    // interior tiles store whole vectors; tiles touching column 0 or n+1 go cell by cell
+    const bool whole = oc0 >= V && oc1 <= n;
+
+    const A w = (A)p.w, cc = (A)p.c, lam = (A)p.lam;
+    const bool dir = (p.bc == DIRICHLET0);
+    const int rb = p.ld * ES, rbf = p.ld_f * ES;
+
+    A win[NL][3][V];
+    A fq[FQ][V];
+#pragma unroll
+    for (int t = 0; t < NL; ++t)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) win[t][k][v] = 0;
+#pragma unroll
+    for (int j = 0; j < FQ; ++j)
+#pragma unroll
+        for (int v = 0; v < V; ++v) fq[j][v] = 0;
+
+    unsigned long long rmax = 0;
+    double rsum = 0.0;
+    // residual window of this wave: rows [ry0, ry1), columns [rc0, rc1), interior only
+    const int ry0 = max(y0, 1), ry1 = min(y1, n + 1);
+    const int rc0 = max(oc0, 1), rc1 = min(oc1, n + 1);
+    // columns of f loaded by this lane: its own aligned columns (VEC, shifted by one
+    // lane afterwards) or exactly the columns its cells need
+    const int fc = VEC ? mc : mc - 1;
+
+    // Rows are prefetched PF ahead into a ring of raw registers; the loop is
+    // unrolled PF times so the ring rotates by renaming, never by moves that would
+    // wait on loads in flight.
+    // (the step count is rounded up to a multiple of PF: the extra steps compute
+    // rows past the band and store nothing, and the loop keeps a single latch)
+    const int sb = y0 - NL, se = sb + (y1 - y0 + 2 * NL + PF - 1) / PF * PF;
+    Raw pf[PF], pff[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        pf[q] = IO::load(row_rsrc(p.in, sb + q, n + 2, rb), mc);
+        pff[q] = IO::load(row_rsrc(p.f, sb + q - 1, n, rbf), fc);
+    }
+    for (int s0 = sb; s0 < se; s0 += PF) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int s = s0 + q;
+            // ---- level 0: row s of phi and of f from the ring, then refill the slot
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                win[0][0][v] = win[0][1][v];
+                win[0][1][v] = win[0][2][v];
+            }
+            IO::unpack(pf[q], win[0][2]);
+#pragma unroll
+            for (int j = FQ - 1; j > 0; --j)
+#pragma unroll
+                for (int v = 0; v < V; ++v) fq[j][v] = fq[j - 1][v];
+            {
+                A fo[V];
+                IO::unpack(pff[q], fo);
+                if constexpr (VEC) {
+                    fq[0][0] = lane_from_left(fo[V - 1]);
+#pragma unroll
+                    for (int v = 1; v < V; ++v) fq[0][v] = fo[v - 1];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) fq[0][v] = fo[v];
+                }
+            }
+            pf[q] = IO::load(row_rsrc(p.in, s + PF, n + 2, rb), mc);
+            pff[q] = IO::load(row_rsrc(p.f, s + PF - 1, n, rbf), fc);
+
+            // ---- levels 1..NL, level t at row s - t
+#pragma unroll
+            for (int t = 1; t <= NL; ++t) {
+                if (s < y0 - NL + 2 * t) break;  // rows this level does not need yet
+                const int r = s - t;
+                const A left = lane_from_left(win[t - 1][1][V - 1]);
+                const A right = lane_from_right(win[t - 1][1][0]);
+                A st[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const A C = win[t - 1][1][v];
+                    A N = win[t - 1][0][v];
+                    A S = win[t - 1][2][v];
+                    A Wn = (v == 0) ? left : win[t - 1][1][v - 1];
+                    A En = (v == V - 1) ? right : win[t - 1][1][v + 1];
+                    if (dir) {
+                        const int col = mc + v;
+                        if (r == 1) N = -C;
+                        if (r == n) S = -C;
+                        if (col == 1) Wn = -C;
+                        if (col == n) En = -C;
+                    }
+                    st[v] = (((N - (A)4 * C) + Wn) + En) + S;
+                }
+                if (t <= K) {
+                    A nv[V];
+                    const bool row_in = (r >= 1 && r <= n);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int col = mc + v;
+                        const A C = win[t - 1][1][v];
+                        const A u = E::round((C + w * st[v]) - lam * fq[t][v]);
+                        const bool inter = row_in && col >= 1 && col <= n;
+                        nv[v] = inter ? u : (dir ? (A)0 : C);
+                    }
+                    if (t < NL) {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            win[t][0][v] = win[t][1][v];
+                            win[t][1][v] = win[t][2][v];
+                            win[t][2][v] = nv[v];
+                        }
+                    }
+                    if (t == K && r >= y0 && r < y1) {
+                        if (dir) {
+                            if (row_in) {
+                                const auto ro = row_rsrc(p.out, r, n + 2, rb);
+                                store_cols<T, V, VEC>(ro, mc, rc0, rc1, whole, nv, false);
+                                if (!whole) {
+                                    // edge ghosts of this row: -(column 1), -(column n)
+#pragma unroll
+                                    for (int v = 0; v < V; ++v) {
+                                        const int col = mc + v;
+                                        const bool mine = col >= rc0 && col < rc1;
+                                        Store1<T>::st(ro, 0, mine && col == 1, -nv[v]);
+                                        Store1<T>::st(ro, n + 1, mine && col == n, -nv[v]);
+                                    }
+                                }
+                                // ghost rows 0 and n+1 mirror rows 1 and n
+                                if (r == 1)
+                                    store_cols<T, V, VEC>(row_rsrc(p.out, 0, n + 2, rb), mc, rc0, rc1,
+                                                          whole, nv, true);
+                                if (r == n)
+                                    store_cols<T, V, VEC>(row_rsrc(p.out, n + 1, n + 2, rb), mc, rc0,
+                                                          rc1, whole, nv, true);
+                            }
+                        } else {
+                            const bool ghost_row = (r == 0 || r == n + 1);
+                            const int lo = max(oc0, ghost_row ? 1 : 0);
+                            const int hi = min(oc1, ghost_row ? n + 1 : n + 2);
+                            store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, lo, hi,
+                                                  whole && !ghost_row, nv, false);
+                        }
+                    }
+                }
+                if (RM != RES_NONE && t == RL && r >= ry0 && r < ry1) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int col = mc + v;
+                        const A rr = fq[t][v] - cc * st[v];
+                        const double rd = (double)rr;
+                        const unsigned long long bits =
+                            (unsigned long long)__double_as_longlong(fabs(rd));
+                        const bool mine = col >= rc0 && col < rc1;
+                        rmax = (mine && bits > rmax) ? bits : rmax;
+                        rsum += mine ? rd * rd : 0.0;
+                    }
+                }
+            }
+        }
+    }
+
+    if (RM != RES_NONE) {
+#pragma unroll
+        for (int off = WAVE / 2; off > 0; off >>= 1) {
+            const unsigned long long om = __shfl_xor(rmax, off, WAVE);
+            const double os = __shfl_xor(rsum, off, WAVE);
+            rmax = om > rmax ? om : rmax;
+            // fixed pairing: the lower lane's value always comes first
+            rsum = (lane & off) ? (os + rsum) : (rsum + os);
+        }
+        if (lane == 0) {
+            p.pmax[tile] = rmax;
+            p.psum[tile] = rsum;
+        }
+    }
+}
+
+using LaunchFn = void (*)(const KArgs &, int, hipStream_t);
+
+template <typename T, int K, int RM, bool VEC>
+void launch_inst(const KArgs &ka, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL((relax_tb_kernel<T, VecOf<T>::V, K, RM, PREFETCH, VEC>), dim3(nblocks),
+                       dim3(WAVE * WAVES_PER_BLOCK), 0, s, ka);
+}
+
+template <typename T, int K, bool VEC>
+LaunchFn pick_rm(int rm)
+{
+    switch (rm) {
+    case RES_NONE: return &launch_inst<T, K, RES_NONE, VEC>;
+    case RES_LAGGED: return &launch_inst<T, K, RES_LAGGED, VEC>;
+    default: return &launch_inst<T, K, RES_FINAL, VEC>;
+    }
+}
+
+template <typename T, bool VEC>
+LaunchFn pick_k(int k, int rm)
+{
+    switch (k) {
+    case 1: return pick_rm<T, 1, VEC>(rm);
+    case 2: return pick_rm<T, 2, VEC>(rm);
+    case 3: return pick_rm<T, 3, VEC>(rm);
+    case 4: return pick_rm<T, 4, VEC>(rm);
+    case 5: return pick_rm<T, 5, VEC>(rm);
+    case 6: return pick_rm<T, 6, VEC>(rm);
+    case 7: return pick_rm<T, 7, VEC>(rm);
+    case 8: return pick_rm<T, 8, VEC>(rm);
+    default: return nullptr;
+    }
+}
+
+
+
+// Per-element-type launcher tables, each compiled in its own translation unit.
+LaunchFn pick_f64(int k, int rm, bool vec);
+LaunchFn pick_f32(int k, int rm, bool vec);
+LaunchFn pick_bf16(int k, int rm, bool vec);
+
+}  // namespace relax_detail
+}  // namespace px
