@@ -83,10 +83,11 @@ def variants(px, ctx, norms):
         d = setup(N, dt)
         ctx.reserve(N, d["phi0"].stride(0), px.dtype_code(d["phi0"]))
         for tb in range(1, 9):
-            t = time_region(relax_fn(px, d, ctx, norms, tb), reps=2, warmup=1)
+            reps = 3
+            t = time_region(relax_fn(px, d, ctx, norms, tb), reps=reps, warmup=2)
             launches = -(-SWEEPS // tb)
-            gcell = N * N * SWEEPS / t / 1e9
-            gbs = BYTES_PER_CELL[dt] * N * N * launches / t / 1e9
+            gcell = N * N * SWEEPS * reps / t / 1e9
+            gbs = BYTES_PER_CELL[dt] * N * N * launches * reps / t / 1e9
             out[f"fused_{dt}_k{tb}"] = {"gcell_s": round(gcell, 2), "alg_GBs": round(gbs, 1),
                                         "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
             log(f"  fused {dt} k={tb}: {gcell:8.1f} Gcell/s  {gbs:7.1f} GB/s algorithmic")
@@ -135,8 +136,8 @@ def cpu_baseline(sample_sweeps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--tblock", type=int, default=BENCH_TBLOCK["f64"])
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")

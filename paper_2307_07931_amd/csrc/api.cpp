@@ -483,7 +483,7 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
         const int nblk = pointwise_num_blocks(n);
         if ((st = ensure_partials(ctx, (size_t)nblk))) return st;
         // step 0: oth = phi (copy with ghosts per bc), r = f - L phi
-        PX_HIP(refine_launch(lowp, (const double *)cur, nullptr, (double *)oth, n, ld, (const double *)f,
+        PX_HIP(refine_launch(lowp, (const double *)cur, nullptr, 0, (double *)oth, n, ld, (const double *)f,
                              ld_f, 1.0 / (h * h), bc, rl, ldl, partials(ctx), s),
                "refine kernel launch");
         PX_HIP(reduce_partials(partials(ctx), nblk, ctx->norms_dev, s), "norm reduction launch");
@@ -502,7 +502,7 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
                                  std::min(k, inner), bc, RES_NONE, nullptr, s)))
                 return st;
             // outer: oth = cur + delta (FP64), r = f - L oth
-            PX_HIP(refine_launch(lowp, (const double *)cur, db, (double *)oth, n, ld, (const double *)f, ld_f,
+            PX_HIP(refine_launch(lowp, (const double *)cur, db, ldl, (double *)oth, n, ld, (const double *)f, ld_f,
                                  1.0 / (h * h), bc, rl, ldl, partials(ctx), s),
                    "refine kernel launch");
             PX_HIP(reduce_partials(partials(ctx), nblk, ctx->norms_dev, s), "norm reduction launch");

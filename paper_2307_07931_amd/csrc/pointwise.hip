@@ -199,7 +199,7 @@ __global__ __launch_bounds__(BX) void zero_grid_kernel(T *__restrict__ p, int n,
 // FP64 outer refinement step around a low-precision inner solve.
 template <typename L>
 __global__ __launch_bounds__(BX) void refine_kernel(const double *__restrict__ phi_in,
-                                                    const L *__restrict__ delta,
+                                                    const L *__restrict__ delta, int ld_d,
                                                     double *__restrict__ phi_out, int n, int ld,
                                                     const double *__restrict__ f, int ld_f,
                                                     double c, int bc, L *__restrict__ r_low,
@@ -214,9 +214,9 @@ __global__ __launch_bounds__(BX) void refine_kernel(const double *__restrict__ p
     if (j <= n) {
         // updated value of a cell: interior cells add delta, ghosts do not change
         auto upd = [&](int ii, int jj) -> double {
-            const size_t q = (size_t)ii * ld + jj;
-            double v = phi_in[q];
-            if (delta && ii >= 1 && ii <= n && jj >= 1 && jj <= n) v = v + (double)Elem<L>::load(delta[q]);
+            double v = phi_in[(size_t)ii * ld + jj];
+            if (delta && ii >= 1 && ii <= n && jj >= 1 && jj <= n)
+                v = v + (double)Elem<L>::load(delta[(size_t)ii * ld_d + jj]);
             return v;
         };
         const double C = upd(i, j);
@@ -383,18 +383,18 @@ hipError_t zero_grid_launch(int dtype, void *p, int n, int ld, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t refine_launch(int lowp, const double *phi_in, const void *delta, double *phi_out,
+hipError_t refine_launch(int lowp, const double *phi_in, const void *delta, int ld_d, double *phi_out,
                          int n, int ld, const double *f, int ld_f, double c, int bc, void *r_low,
                          int ld_r, Partials part, hipStream_t s)
 {
     const dim3 g = interior_grid(n);
     if (lowp == F32)
         hipLaunchKernelGGL((refine_kernel<float>), g, dim3(BX), 0, s, phi_in, (const float *)delta,
-                           phi_out, n, ld, f, ld_f, c, bc, (float *)r_low, ld_r, part.max_bits,
+                           ld_d, phi_out, n, ld, f, ld_f, c, bc, (float *)r_low, ld_r, part.max_bits,
                            part.sum);
     else if (lowp == BF16)
         hipLaunchKernelGGL((refine_kernel<bf16>), g, dim3(BX), 0, s, phi_in, (const bf16 *)delta,
-                           phi_out, n, ld, f, ld_f, c, bc, (bf16 *)r_low, ld_r, part.max_bits,
+                           ld_d, phi_out, n, ld, f, ld_f, c, bc, (bf16 *)r_low, ld_r, part.max_bits,
                            part.sum);
     else
         return hipErrorInvalidValue;

@@ -94,9 +94,10 @@ hipError_t jacobi_launch(int dtype, void *phi, int n, int ld, const void *sv, in
 hipError_t copy_grid_launch(int dtype, const void *in, void *out, int n, int ld, hipStream_t s);
 
 // Mixed-precision refinement pieces (FP64 outer step).
-// phi_out = phi_in + delta (interior; delta of dtype lowp, may be NULL for 0),
-// r = f - L phi_out written in FP64 partial norms and as lowp into r_low.
-hipError_t refine_launch(int lowp, const double *phi_in, const void *delta, double *phi_out,
+// phi_out = phi_in + delta (interior; delta of dtype lowp with leading dimension
+// ld_d, may be NULL for 0), r = f - L phi_out: FP64 partial norms, and r rounded
+// to lowp into r_low.
+hipError_t refine_launch(int lowp, const double *phi_in, const void *delta, int ld_d, double *phi_out,
                          int n, int ld, const double *f, int ld_f, double c, int bc,
                          void *r_low, int ld_r, Partials part, hipStream_t s);
 hipError_t zero_grid_launch(int dtype, void *p, int n, int ld, hipStream_t s);

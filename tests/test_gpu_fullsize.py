@@ -1,0 +1,53 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+4096 x 4096, f ~ U[-1,1] (seed 2), phi0 = 0, 200 sweeps at the benchmark's sweeps per
+launch and default tile shape, FP64 and FP32.  The oracle cannot run 200 full sweeps in
+a test's time budget, so the comparison is sampled:
+
+* light-cone windows: the oracle relaxes windows of the grid (corners, edges, centre)
+  with their interface ghosts held fixed; every window cell at least 200 cells from an
+  interface is exact and must match the GPU bit for bit;
+* the reported norms must equal the oracle's residual norms of the GPU's own output
+  (max bit for bit, sum of squares to 1e-12) -- a property that holds at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2307_07931_amd as px
+import workloads as W
+from bench import BENCH_TBLOCK, N, OMEGA, SWEEPS
+
+import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    H.require_gpu()
+    c = px.Context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_fullsize_sampled_windows_and_norms(ctx, dt):
+    n, S = N, SWEEPS
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    f = W.uniform_rhs(n, W.SEED_UNIFORM_4096)
+    phi0 = np.zeros((n + 2, n + 2))
+    print(f"case: full size {dt} n={n} sweeps={S} tblock={BENCH_TBLOCK[dt]}", flush=True)
+    g, norms = H.gpu_relax(phi0, f, n, h, lam, S, dt, ctx, tblock=BENCH_TBLOCK[dt])
+    Wn = 2 * S + 64
+    starts = (1, (n - Wn) // 2, n - Wn + 1)
+    compared = 0
+    for r0 in starts:
+        for c0 in starts:
+            compared += H.window_check(g, phi0, f, n, h, lam, S, r0, c0, Wn, dt)
+    assert compared > 9 * 60 * 60
+    # norms reported by the kernel == oracle residual norms of the kernel's own output
+    gi = np.ascontiguousarray(g[:, :n + 2])
+    _, mx, sq = oracle.residual(gi, H.oracle_input(f, dt), n, h)
+    H.assert_norms(norms, mx, sq, n=n)

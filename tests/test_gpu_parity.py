@@ -43,7 +43,7 @@ def test_manufactured_64_fp64_matches_oracle_and_closed_form(ctx, tblock):
     g, norms = H.gpu_relax(phi0, f, n, h, lam, N, "f64", ctx, tblock=tblock)
     ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, N, "f64")
     H.assert_grid_bitwise(g, ref, n)
-    H.assert_norms(norms, mx, sq)
+    H.assert_norms(norms, mx, sq, n=n)
     cf = exact.manufactured_closed_form(n, N, OMEGA)
     assert norms[0] == pytest.approx(cf["res_max_final"], rel=1e-12)
     err = np.abs(g[1:n + 1, 1:n + 1] - W.manufactured_solution(n)).max()
@@ -76,7 +76,7 @@ def test_relax_matches_oracle(ctx, dt, n, nsweeps, tblock, bc, resmode):
     ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, nsweeps, dt, bc=bc, resmode=resmode)
     H.assert_grid_bitwise(g, ref, n)
     if resmode != px.RES_NONE:
-        H.assert_norms(norms, mx, sq)
+        H.assert_norms(norms, mx, sq, n=n)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
@@ -93,7 +93,7 @@ def test_all_tblocks_and_tile_shapes_agree(ctx, dt):
             print(f"case: {dt} rows={rows} tblock={tb}", flush=True)
             g, norms = H.gpu_relax(phi0, f, n, h, lam, N, dt, ctx, tblock=tb)
             H.assert_grid_bitwise(g, ref, n, what=f"rows={rows} tblock={tb}")
-            H.assert_norms(norms, mx, sq)
+            H.assert_norms(norms, mx, sq, n=n)
     ctx.set_tile_rows(0)
 
 
@@ -110,7 +110,7 @@ def test_unaligned_layouts(ctx, dt):
         print(f"case: {dt} ld={ld} ld_f={ld_f} f_aligned={fal}", flush=True)
         g, norms = H.gpu_relax(phi0, f, n, h, lam, N, dt, ctx, tblock=3, ld=ld, ld_f=ld_f, f_aligned=fal)
         H.assert_grid_bitwise(g, ref, n, what=f"ld={ld} ld_f={ld_f}")
-        H.assert_norms(norms, mx, sq)
+        H.assert_norms(norms, mx, sq, n=n)
 
 
 def test_node_centred_ghost_fixed_closed_form(ctx):
@@ -202,7 +202,7 @@ def test_residual_matches_oracle(ctx, dt, bc):
     torch.cuda.synchronize()
     rr, mx, sq = oracle.residual(H.oracle_input(phi, dt), H.oracle_input(f, dt), n, h, bc=bc)
     assert np.array_equal(H.bits(H.to_storage_np(r, dt)), H.bits(rr))
-    H.assert_norms(norms.cpu().numpy(), mx, sq)
+    H.assert_norms(norms.cpu().numpy(), mx, sq, n=n)
 
 
 @pytest.mark.parametrize("dt", ["f64", "f32"])
