@@ -292,42 +292,33 @@ __device__ __forceinline__ void store_cols(__amdgpu_buffer_rsrc_t r, int col0, i
     for (int v = 0; v < V; ++v) Store1<T>::st(r, col0 + v, col0 + v >= lo && col0 + v < hi, x[v]);
 }
 
-template <typename T, int V, int K, int RM, int PF, bool VEC>
-__global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const KArgs p)
+// Geometry of one wave's tile (wave-uniform except mc).
+struct Tile {
+    int n, oc0, oc1, mc, y0, y1;
+    bool whole;  // only whole vectors of interior columns to store
+};
+
+// The streaming loop of one tile.  EDGE = false is the interior-tile path: every cell
+// the wave computes is an interior cell, so no boundary substitution, no ghost writes
+// and no selects on the update -- the common case, taken when the tile's loaded
+// columns and needed rows all lie in [1, n].
+template <typename T, int V, int K, int RM, int PF, bool VEC, bool EDGE>
+__device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigned long long &rmax,
+                                         double &rsum)
 {
     using E = Elem<T>;
     using A = typename E::A;
     using IO = Io<T, V, VEC>;
     using Raw = typename IO::Raw;
-    constexpr int NL = K + (RM == RES_FINAL ? 1 : 0);  // pipeline levels
-    constexpr int RL = (RM == RES_FINAL) ? K + 1 : K;  // level that takes the residual
-    constexpr int FQ = RL + 1;                         // f rows kept in registers
+    constexpr int NL = K + (RM == RES_FINAL ? 1 : 0);
+    constexpr int RL = (RM == RES_FINAL) ? K + 1 : K;
+    constexpr int FQ = RL + 1;
     constexpr int ES = (int)sizeof(T);
-
-    // XCD-aware block order: block b runs on XCD b % 8; give each XCD a contiguous
-    // run of tiles so neighbouring tiles (shared halo rows/columns) share an L2.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int nb8 = nb & ~7;
-    const int lb = (b < nb8) ? ((b & 7) * (nb8 >> 3) + (b >> 3)) : b;
-    // the wave index is uniform across the wave; say so, so every tile quantity and
-    // every row descriptor lives in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int tile = lb * WAVES_PER_BLOCK + wave;
-    if (tile >= p.ntiles) return;  // wave-uniform; waves never synchronise
-    const int lane = threadIdx.x & (WAVE - 1);
-
-    const int n = p.n;
-    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-    const int oc0 = p.col_origin + tx * p.stride;  // output columns [oc0, oc1)
-    const int oc1 = min(oc0 + p.stride, n + 2);
-    const int mc = oc0 - p.halo + lane * V;        // first column held by this lane
-    const int y0 = ty * p.rows, y1 = min(y0 + p.rows, n + 2);
-    // interior tiles store whole vectors; tiles touching column 0 or n+1 go cell by cell
-    const bool whole = oc0 >= V && oc1 <= n;
-
-    const A w = (A)p.w, cc = (A)p.c, lam = (A)p.lam;
+    const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
+    const bool whole = tl.whole;
     const bool dir = (p.bc == DIRICHLET0);
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
+    const A w = (A)p.w, cc = (A)p.c, lam = (A)p.lam;
 
     A win[NL][3][V];
     A fq[FQ][V];
@@ -342,8 +333,6 @@ __global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const K
 #pragma unroll
         for (int v = 0; v < V; ++v) fq[j][v] = 0;
 
-    unsigned long long rmax = 0;
-    double rsum = 0.0;
     // residual window of this wave: rows [ry0, ry1), columns [rc0, rc1), interior only
     const int ry0 = max(y0, 1), ry1 = min(y1, n + 1);
     const int rc0 = max(oc0, 1), rc1 = min(oc1, n + 1);
@@ -408,7 +397,7 @@ __global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const K
                     A S = win[t - 1][2][v];
                     A Wn = (v == 0) ? left : win[t - 1][1][v - 1];
                     A En = (v == V - 1) ? right : win[t - 1][1][v + 1];
-                    if (dir) {
+                    if (EDGE && dir) {
                         const int col = mc + v;
                         if (r == 1) N = -C;
                         if (r == n) S = -C;
@@ -426,7 +415,7 @@ __global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const K
                         const A C = win[t - 1][1][v];
                         const A u = E::round((C + w * st[v]) - lam * fq[t][v]);
                         const bool inter = row_in && col >= 1 && col <= n;
-                        nv[v] = inter ? u : (dir ? (A)0 : C);
+                        nv[v] = EDGE ? (inter ? u : (dir ? (A)0 : C)) : u;
                     }
                     if (t < NL) {
 #pragma unroll
@@ -437,7 +426,11 @@ __global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const K
                         }
                     }
                     if (t == K && r >= y0 && r < y1) {
-                        if (dir) {
+                        if constexpr (!EDGE) {
+                            // interior tile: interior rows and columns only, whole vectors
+                            store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv,
+                                                  false);
+                        } else if (dir) {
                             if (row_in) {
                                 const auto ro = row_rsrc(p.out, r, n + 2, rb);
                                 store_cols<T, V, VEC>(ro, mc, rc0, rc1, whole, nv, false);
@@ -484,6 +477,47 @@ __global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const K
             }
         }
     }
+
+}
+
+template <typename T, int V, int K, int RM, int PF, bool VEC>
+__global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const KArgs p)
+{
+    using E = Elem<T>;
+    using A = typename E::A;
+    constexpr int NL = K + (RM == RES_FINAL ? 1 : 0);  // pipeline levels
+
+    // XCD-aware block order: block b runs on XCD b % 8; give each XCD a contiguous
+    // run of tiles so neighbouring tiles (shared halo rows/columns) share an L2.
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int nb8 = nb & ~7;
+    const int lb = (b < nb8) ? ((b & 7) * (nb8 >> 3) + (b >> 3)) : b;
+    // the wave index is uniform across the wave; say so, so every tile quantity and
+    // every row descriptor lives in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int tile = lb * WAVES_PER_BLOCK + wave;
+    if (tile >= p.ntiles) return;  // wave-uniform; waves never synchronise
+    const int lane = threadIdx.x & (WAVE - 1);
+
+    const int n = p.n;
+    const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+    const int oc0 = p.col_origin + tx * p.stride;  // output columns [oc0, oc1)
+    const int oc1 = min(oc0 + p.stride, n + 2);
+    const int mc = oc0 - p.halo + lane * V;        // first column held by this lane
+    const int y0 = ty * p.rows, y1 = min(y0 + p.rows, n + 2);
+    // tiles whose outputs avoid columns 0, 1, n, n+1 store whole vectors
+    const bool whole = oc0 >= V && oc1 <= n;
+    // interior tile: loaded columns and needed rows all inside [1, n]
+    const bool interior = (mc - lane * V) >= 1 && (mc - lane * V) + WAVE * V - 1 <= n &&
+                          y0 - NL >= 1 && y1 + NL - 1 <= n;
+    const Tile tl{n, oc0, oc1, mc, y0, y1, whole};
+    unsigned long long rmax = 0;
+    double rsum = 0.0;
+    if (interior)
+        run_tile<T, V, K, RM, PF, VEC, false>(p, tl, rmax, rsum);
+    else
+        run_tile<T, V, K, RM, PF, VEC, true>(p, tl, rmax, rsum);
+
 
     if (RM != RES_NONE) {
 #pragma unroll
