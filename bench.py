@@ -30,9 +30,13 @@ HBM_PEAK_GBS = 8000.0
 N = 4096
 SWEEPS = 200
 OMEGA = 2.0 / 3.0
-# launch configuration timed by default (also the full-size parity tests' configuration)
-BENCH_TBLOCK = {"f64": 8, "f32": 8}
 BYTES_PER_CELL = {"f64": 24, "f32": 12, "bf16": 6}  # read phi + f, write phi', per launch
+# FP64 operations per cell per sweep: stencil 4 adds + 1 multiply, update 2 multiplies +
+# 2 adds.  Bit-exactness forbids fused multiply-add, so the attainable FP64 vector rate
+# is one add or multiply per lane per clock: 256 CUs x 64 lanes x 2.4 GHz = 39.3 TFLOP/s
+# (the 78.6 TFLOP/s figure counts an FMA as two).
+FLOPS_PER_CELL_SWEEP = 9
+FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
 
@@ -138,7 +142,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--tblock", type=int, default=BENCH_TBLOCK["f64"])
+    ap.add_argument("--tblock", type=int, default=0,
+                    help="sweeps per launch; 0 = autotuned (k, tile rows) before timing")
+    ap.add_argument("--rows", type=int, default=0, help="tile rows (with --tblock; 0 = default)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 1 GiB device-to-device copy 5 times (the known-size kernel "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=24)
@@ -153,6 +162,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": a.numel() * 8,
+                          "bytes_written": b.numel() * 8, "dispatches": 5}), flush=True)
+        return
     px.lib()
     torch.cuda.set_device(0)
     ctx = px.Context(0)
@@ -161,6 +179,13 @@ def main():
     d = setup(N, "f64")
     ctx.reserve(N, d["phi0"].stride(0), px.F64)
     tb = args.tblock
+    rows = None
+    if args.rows:
+        ctx.set_tile_rows(args.rows)
+        rows = args.rows
+    if tb == 0:
+        tb, rows, g = px.autotune(d["phi0"], d["phi_out"], N, d["f"], ctx)
+        log(f"autotuned: {tb} sweeps per launch, {rows} rows per tile ({g:.1f} Gcell/s in the tuner)")
     step = relax_fn(px, d, ctx, norms, tb)
     log(f"timing {args.steps} steps of {SWEEPS} sweeps, {N}^2 FP64, {tb} sweeps per launch")
     t = time_region(step, reps=args.steps, warmup=args.warmup)
@@ -173,6 +198,18 @@ def main():
     log(f"step {ms:.3f} ms -> {value:.1f} Gcell-updates/s; relax launch {per_launch_s * 1e6:.1f} us "
         f"-> {achieved:.1f} GB/s algorithmic ({achieved / HBM_PEAK_GBS:.1%} of 8 TB/s)")
     res_max = float(norms[0])
+    hbm_view = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": BYTES_PER_CELL["f64"] * N * N}
+    if tb == 1:
+        roofline = {"bound": "hbm", **hbm_view, "traffic": None}
+    else:
+        # several sweeps per launch: HBM bytes per cell-update fall to 24/k and the
+        # kernel is bound by vector ALU issue
+        tflops = FLOPS_PER_CELL_SWEEP * N * N * tb / per_launch_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(FP64_NOFMA_PEAK_TFLOPS, 1),
+                    "unit": "TFLOP/s", "frac": round(tflops / FP64_NOFMA_PEAK_TFLOPS, 4), "traffic": None,
+                    "alg_flops_per_launch": FLOPS_PER_CELL_SWEEP * N * N * tb, "hbm_view": hbm_view}
+    roofline["kernel"] = f"relax_tb_kernel<double,2,{tb},*> ({rows or 'default'} rows per tile)"
 
     var = None if args.no_variants else variants(px, ctx, norms)
     cpu = None if args.no_cpu else cpu_baseline(args.cpu_sweeps)
@@ -191,13 +228,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "poisson2d_fused_jacobi_4096sq_fp64_200sweeps", "n": N,
-                   "sweeps_per_step": SWEEPS, "sweeps_per_launch": tb, "omega": OMEGA,
+                   "sweeps_per_step": SWEEPS, "sweeps_per_launch": tb, "tile_rows": rows,
+                   "omega": OMEGA,
                    "rhs": "uniform[-1,1] PCG64 seed 2", "phi0": 0, "bc": "dirichlet0_cell_centred",
                    "residual": "final max-norm and sum of squares"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"relax_tb_kernel<double,2,{tb},*>",
-                     "alg_bytes_per_launch": BYTES_PER_CELL["f64"] * N * N},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "final_res_max": res_max,
         "variants": var,

@@ -96,6 +96,19 @@ int px_ctx_reserve(px_ctx *ctx, int n, int ld, int dtype);
  * A tuning knob; any value in [1, 4096] gives identical results. */
 int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
 
+/*
+ * Autotuner: times the fused relaxation on the caller's buffers for every
+ * sweeps-per-launch k in 1..8 and a list of tile heights, and remembers the
+ * fastest (k, rows) in ctx for this (dtype, n, ld).  Later calls with
+ * tblock == 0 on such a grid use it (explicit tblock or px_ctx_set_tile_rows
+ * override it).  phi_in is only read; phi_out is overwritten with scratch
+ * iterates; f as in px_relax_fused.  Waits on `stream`.  best_k, best_rows and
+ * gcells (cell-updates per second / 1e9 of the winner) may be NULL.
+ */
+int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f,
+                int ld_f, int bc, px_ctx *ctx, void *stream, int *best_k, int *best_rows,
+                double *gcells);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *px_last_error(void);
 const char *px_version(void);

@@ -56,8 +56,8 @@ class _SolveStats(ctypes.Structure):
 
 
 EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
-           "px_last_error", "px_version", "px_apply_stencil", "px_residual", "px_jacobi_update",
-           "px_relax_fused", "px_solve")
+           "px_autotune", "px_last_error", "px_version", "px_apply_stencil", "px_residual",
+           "px_jacobi_update", "px_relax_fused", "px_solve")
 
 _lib = None
 
@@ -85,7 +85,9 @@ def lib() -> ctypes.CDLL:
     L.px_relax_fused.argtypes = [P, P, I, I, I, P, I, D, D, I, I, I, I, P, P, P]
     L.px_solve.argtypes = [P, I, I, I, P, I, D, D, ctypes.POINTER(_SolveOpts),
                            ctypes.POINTER(_SolveStats), P, P]
-    for nm in ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
+    L.px_autotune.argtypes = [P, P, I, I, I, P, I, I, P, P, ctypes.POINTER(I), ctypes.POINTER(I),
+                              ctypes.POINTER(D)]
+    for nm in ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
                "px_apply_stencil", "px_residual", "px_jacobi_update", "px_relax_fused", "px_solve"):
         getattr(L, nm).restype = I
     _lib = L
@@ -235,6 +237,20 @@ def relax_fused(phi_in, phi_out, n, f, h, lam, nsweeps, ctx: Context, tblock=0,
                                 float(h), float(lam), int(nsweeps), int(tblock), int(bc), int(resmode),
                                 _ptr(norms), ctx.handle, _stream_handle(stream)))
     return phi_out
+
+
+def autotune(phi_in, phi_out, n, f, ctx: Context, bc=BC_DIRICHLET0, stream=None):
+    """Times (sweeps per launch, tile rows) candidates on these buffers and stores the
+    fastest in ctx for this grid; returns (k, rows, Gcell-updates/s of the winner)."""
+    ld = _ld(phi_in, n + 2, n + 2, "phi_in")
+    if _ld(phi_out, n + 2, n + 2, "phi_out") != ld:
+        raise ValueError("phi_in and phi_out must share ld")
+    ldf = _ld(f, n, n, "f")
+    k, rows, g = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().px_autotune(_ptr(phi_in), _ptr(phi_out), n, ld, dtype_code(phi_in), _ptr(f), ldf,
+                             int(bc), ctx.handle, _stream_handle(stream), ctypes.byref(k),
+                             ctypes.byref(rows), ctypes.byref(g)))
+    return k.value, rows.value, g.value
 
 
 @dataclass

@@ -16,9 +16,15 @@
 
 using namespace px;
 
+struct px_tuned {
+    int n = 0, ld = 0, k = 0, rows = 0;
+    double gcells = 0.0;
+};
+
 struct px_ctx {
     int device = 0;
     int tile_rows = 0;
+    px_tuned tuned[3];  // per dtype: autotuned (k, rows) for one (n, ld)
     // ping-pong grid (any dtype) for multi-launch relaxation
     void *grid = nullptr;
     size_t grid_bytes = 0;
@@ -157,13 +163,28 @@ int ensure_mix(px_ctx *ctx, size_t bytes)
     return PX_OK;
 }
 
-int default_tblock(int dtype, int n)
+const px_tuned *tuned_for(const px_ctx *ctx, int dtype, int n, int ld)
 {
-    // 8 sweeps per launch is fastest at every size measured (large grids: fewest
-    // passes over HBM; small grids: fewest launches).
-    (void)dtype;
-    (void)n;
+    const px_tuned &t = ctx->tuned[dtype];
+    return (t.k > 0 && t.n == n && t.ld == ld) ? &t : nullptr;
+}
+
+int default_tblock(const px_ctx *ctx, int dtype, int n, int ld)
+{
+    if (const px_tuned *t = tuned_for(ctx, dtype, n, ld)) return t->k;
+    // untuned: 8 sweeps per launch was fastest at every size measured (large grids:
+    // fewest passes over HBM; small grids: fewest launches)
     return 8;
+}
+
+// Tile height for a launch of `ks` sweeps: explicit override, then the tuned value
+// (when the tuned k is the one launched), then the built-in default.
+int pick_rows(const px_ctx *ctx, int dtype, int n, int ld, int ks)
+{
+    if (ctx->tile_rows > 0) return ctx->tile_rows;
+    if (const px_tuned *t = tuned_for(ctx, dtype, n, ld))
+        if (t->k == ks) return t->rows;
+    return relax_default_rows(dtype, n, ks);
 }
 
 Partials partials(px_ctx *ctx) { return Partials{ctx->pmax, ctx->psum}; }
@@ -172,7 +193,7 @@ Partials partials(px_ctx *ctx) { return Partials{ctx->pmax, ctx->psum}; }
 // last launch writes dst.  src is only read.  tmp may be NULL when one launch.
 int run_sweeps(px_ctx *ctx, int dtype, const void *src, void *dst, void *tmp, int n, int ld,
                const void *f, int ld_f, double h, double lambda, int nsweeps, int k, int bc,
-               int resmode, double *norms, hipStream_t s)
+               int resmode, double *norms, hipStream_t s, int forced_rows = 0)
 {
     const int L = (nsweeps + k - 1) / k;
     const double c = 1.0 / (h * h);
@@ -195,7 +216,7 @@ int run_sweeps(px_ctx *ctx, int dtype, const void *src, void *dst, void *tmp, in
         a.bc = bc;
         a.sweeps = ks;
         a.resmode = (i == L - 1) ? resmode : RES_NONE;
-        a.rows = ctx->tile_rows > 0 ? ctx->tile_rows : relax_default_rows(dtype, n, ks);
+        a.rows = forced_rows > 0 ? forced_rows : pick_rows(ctx, dtype, n, ld, ks);
         a.part = partials(ctx);
         if (a.resmode != RES_NONE) {
             int st = ensure_partials(ctx, (size_t)relax_num_waves(dtype, n, ks, a.resmode, a.rows));
@@ -277,8 +298,7 @@ int px_ctx_reserve(px_ctx *ctx, int n, int ld, int dtype)
     size_t parts = (size_t)pointwise_num_blocks(n);
     for (int k = 1; k <= 8; ++k)
         for (int rm = RES_LAGGED; rm <= RES_FINAL; ++rm) {
-            const int rows = ctx->tile_rows > 0 ? ctx->tile_rows : relax_default_rows(dtype, n, k);
-            parts = std::max(parts, (size_t)relax_num_waves(dtype, n, k, rm, rows));
+            parts = std::max(parts, (size_t)relax_num_waves(dtype, n, k, rm, pick_rows(ctx, dtype, n, ld, k)));
         }
     if ((st = ensure_partials(ctx, parts))) return st;
     return ensure_norms(ctx);
@@ -369,7 +389,7 @@ int px_relax_fused(const void *phi_in, void *phi_out, int n, int ld, int dtype, 
             return residual_into(ctx, dtype, phi_in, n, ld, f, ld_f, h, bc, nullptr, 0, norms, s);
         return PX_OK;
     }
-    const int k = tblock ? tblock : default_tblock(dtype, n);
+    const int k = tblock ? tblock : default_tblock(ctx, dtype, n, ld);
     void *tmp = nullptr;
     if ((nsweeps + k - 1) / k > 1) {
         if ((st = ensure_grid(ctx, gb))) return st;
@@ -377,6 +397,75 @@ int px_relax_fused(const void *phi_in, void *phi_out, int n, int ld, int dtype, 
     }
     return run_sweeps(ctx, dtype, phi_in, phi_out, tmp, n, ld, f, ld_f, h, lambda, nsweeps, k, bc,
                       resmode, norms, s);
+}
+
+int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f, int ld_f,
+                int bc, px_ctx *ctx, void *stream, int *best_k, int *best_rows, double *gcells)
+{
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = check_ptr(phi_in, dtype, "phi_in")) || (st = check_ptr(phi_out, dtype, "phi_out")))
+        return st;
+    if ((st = check_flat(f, n, ld_f, dtype, "f"))) return st;
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    const size_t gb = grid_bytes(n, ld, dtype);
+    if (overlap(phi_in, gb, phi_out, gb)) return fail(PX_EALIAS, "phi_out overlaps phi_in");
+    if (overlap(f, flat_bytes(n, ld_f, dtype), phi_out, gb)) return fail(PX_EALIAS, "phi_out overlaps f");
+    if ((st = set_device(ctx))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // Candidate tile heights: short bands give more waves, long bands less halo
+    // recomputation; the best also depends on how the wave count divides the
+    // resident wave slots, so the list is dense.
+    static const int ROWS[] = {8, 12, 16, 20, 24, 28, 32, 36, 40, 44, 48, 56, 64, 80, 96, 128};
+    const double h = 1.0 / n, lambda = 0.25 * h * h * (2.0 / 3.0);
+    hipEvent_t e0, e1;
+    PX_HIP(hipEventCreate(&e0), "hipEventCreate");
+    PX_HIP(hipEventCreate(&e1), "hipEventCreate");
+    int bk = 0, br = 0;
+    double bg = 0.0;
+    int err = PX_OK;
+    for (int k = 1; k <= 8 && !err; ++k) {
+        for (int rows : ROWS) {
+            if (rows > std::max(8, n + 2)) break;
+            // one launch of k sweeps, timed three times after one warm-up launch
+            if ((err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, k, k, bc,
+                                  RES_NONE, nullptr, s, rows)))
+                break;
+            hipError_t he = hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3 && he == hipSuccess && !err; ++rep)
+                err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, k, k, bc,
+                                 RES_NONE, nullptr, s, rows);
+            if (err) break;
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) {
+                err = hip_fail(he, "autotune timing");
+                break;
+            }
+            const double g = ms > 0.f ? 3.0 * k * (double)n * n / (ms * 1e-3) / 1e9 : 0.0;
+            if (g > bg) {
+                bg = g;
+                bk = k;
+                br = rows;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err) return err;
+    px_tuned &t = ctx->tuned[dtype];
+    t.n = n;
+    t.ld = ld;
+    t.k = bk;
+    t.rows = br;
+    t.gcells = bg;
+    if (best_k) *best_k = bk;
+    if (best_rows) *best_rows = br;
+    if (gcells) *gcells = bg;
+    return PX_OK;
 }
 
 int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, double h, double lambda,
@@ -407,7 +496,7 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
     if ((st = ensure_grid(ctx, gb))) return st;
     hipStream_t s = (hipStream_t)stream;
     const int bc = o->bc;
-    const int k = o->tblock ? o->tblock : default_tblock(dtype, n);
+    const int k = o->tblock ? o->tblock : default_tblock(ctx, dtype, n, ld);
 
     auto read_norms = [&](double *dst) -> int {
         PX_HIP(hipMemcpyAsync(ctx->norms_host, ctx->norms_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s),

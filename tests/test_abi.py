@@ -135,6 +135,19 @@ def test_solve_validation(ctx):
                       None) == px.EINVAL
 
 
+def test_autotune_validation(ctx):
+    P = ctypes.c_void_p
+    L = px.lib()
+    assert L.px_autotune(P(FAKE), P(FAKE2), 0, 66, 0, P(FAKE2 * 2), 64, 0, ctx, None, None, None,
+                         None) == px.EINVAL
+    assert L.px_autotune(P(FAKE), P(FAKE + 8), 64, 66, 0, P(FAKE2 * 2), 64, 0, ctx, None, None, None,
+                         None) == px.EALIAS
+    assert L.px_autotune(P(FAKE), P(FAKE2), 64, 66, 0, P(FAKE2 * 2), 64, 9, ctx, None, None, None,
+                         None) == px.EINVAL
+    assert L.px_autotune(P(FAKE), P(FAKE2), 64, 66, 0, P(FAKE2 * 2), 64, 0, None, None, None, None,
+                         None) == px.EINVAL
+
+
 def test_ctx_validation():
     L = px.lib()
     h = ctypes.c_void_p()

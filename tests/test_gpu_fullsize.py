@@ -1,7 +1,7 @@
 """Parity at the benchmark's full size and launch configuration.
 
-4096 x 4096, f ~ U[-1,1] (seed 2), phi0 = 0, 200 sweeps at the benchmark's sweeps per
-launch and default tile shape, FP64 and FP32.  The oracle cannot run 200 full sweeps in
+4096 x 4096, f ~ U[-1,1] (seed 2), phi0 = 0, 200 sweeps in the benchmark's launch
+configuration (autotuned sweeps per launch and tile rows), FP64 and FP32.  The oracle cannot run 200 full sweeps in
 a test's time budget, so the comparison is sampled:
 
 * light-cone windows: the oracle relaxes windows of the grid (corners, edges, centre)
@@ -16,7 +16,9 @@ import pytest
 import oracle
 import paper_2307_07931_amd as px
 import workloads as W
-from bench import BENCH_TBLOCK, N, OMEGA, SWEEPS
+import torch
+
+from bench import N, OMEGA, SWEEPS
 
 import helpers as H
 
@@ -38,8 +40,13 @@ def test_fullsize_sampled_windows_and_norms(ctx, dt):
     lam = OMEGA * h * h / 4.0
     f = W.uniform_rhs(n, W.SEED_UNIFORM_4096)
     phi0 = np.zeros((n + 2, n + 2))
-    print(f"case: full size {dt} n={n} sweeps={S} tblock={BENCH_TBLOCK[dt]}", flush=True)
-    g, norms = H.gpu_relax(phi0, f, n, h, lam, S, dt, ctx, tblock=BENCH_TBLOCK[dt])
+    # the benchmark's launch configuration: autotuned (k, rows) for this grid, tblock = 0
+    pin = H.device_grid(phi0, n, dt)
+    fd = H.device_rhs(f, n, dt)
+    k, rows, _ = px.autotune(pin, torch.zeros_like(pin), n, fd, ctx)
+    del pin, fd
+    print(f"case: full size {dt} n={n} sweeps={S} autotuned k={k} rows={rows}", flush=True)
+    g, norms = H.gpu_relax(phi0, f, n, h, lam, S, dt, ctx, tblock=0)
     Wn = 2 * S + 64
     starts = (1, (n - Wn) // 2, n - Wn + 1)
     compared = 0

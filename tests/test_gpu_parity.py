@@ -123,6 +123,29 @@ def test_node_centred_ghost_fixed_closed_form(ctx):
     assert norms[0] == pytest.approx(cf["res_max_final"], rel=1e-12)
 
 
+@pytest.mark.parametrize("dt", ["f64", "f32"])
+def test_autotuned_configuration_matches_oracle(dt):
+    """The autotuner picks some (k, rows); relaxing with it (tblock = 0) changes no bit."""
+    n, N = 300, 19
+    h, lam = params(n)
+    f = W.uniform_rhs(n, 31)
+    phi0 = W.uniform_phi(n, 32)
+    c = px.Context()
+    pin = H.device_grid(phi0, n, dt)
+    pout = torch.zeros_like(pin)
+    fd = H.device_rhs(f, n, dt)
+    k, rows, g = px.autotune(pin, pout, n, fd, c)
+    assert 1 <= k <= 8 and 8 <= rows <= 128 and g > 0
+    pout.fill_(H.SENTINEL)
+    norms = torch.zeros(2, dtype=torch.float64, device="cuda")
+    px.relax_fused(pin, pout, n, fd, h, lam, N, c, tblock=0, norms=norms)
+    torch.cuda.synchronize()
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, N, dt)
+    H.assert_grid_bitwise(H.to_storage_np(pout, dt), ref, n)
+    H.assert_norms(norms.cpu().numpy(), mx, sq, n=n)
+    c.close()
+
+
 # ----------------------------------------------------- invariants on GPU --
 
 def test_split_run_is_bitwise(ctx):
