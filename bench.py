@@ -137,6 +137,82 @@ def cpu_baseline(sample_sweeps):
                       f"(of the {SWEEPS}), plain three-pass oracle, single thread, {t:.1f} s"}
 
 
+def mixed_workload(px, ctx):
+    """Mixed-precision refinement (FP32 / BF16 inner sweeps, FP64 outer residual and
+    update) against plain FP64 relaxation, on |k|^-2 Gaussian-random-field right-hand
+    sides.  (a) measured time to max|r| <= 1e-10 max|f| at 256^2 and 512^2, with the
+    error of each result against the exact discrete solution (DST); (b) cost per sweep
+    at 8192^2 and the time to the FP64-attainable tolerance extrapolated from it and the
+    closed-form asymptotic rate of the slowest mode."""
+    import math
+    import numpy as np
+    import torch
+    import workloads as W
+    from oracle import exact  # CPU reference for the error of each result
+    out = {"solves": [], "per_sweep_8192": {}}
+    for n in (256, 512):
+        f_host = W.grf_rhs(n, W.SEED_GRF_8192)
+        ex = exact.dst_solve(f_host, 1.0 / n)
+        h = 1.0 / n
+        lam = OMEGA * h * h / 4.0
+        for mode, name, inner in ((px.SOLVE_PLAIN, "plain_f64", 0), (px.SOLVE_MIXED_F32, "mixed_f32", 64),
+                                  (px.SOLVE_MIXED_BF16, "mixed_bf16", 32)):
+            phi = px.alloc_grid(n, torch.float64)
+            f = px.alloc_rhs(n, torch.float64)
+            f[:, :n] = torch.from_numpy(f_host).cuda()
+            st = px.solve(phi, n, f, h, lam, ctx, mode=mode, rtol=1e-10, check_every=2048,
+                          inner_sweeps=inner, raise_on_error=False)
+            err = float(np.abs(phi[1:n + 1, 1:n + 1].cpu().numpy() - ex).max() / np.abs(ex).max())
+            rec = {"n": n, "mode": name, "status": st.status, "sweeps": st.sweeps, "seconds": round(st.seconds, 3),
+                   "rel_res_max": st.rel_res_max, "rel_err_vs_exact": err}
+            out["solves"].append(rec)
+            log(f"  mixed/{n}: {rec}")
+    # (b) 8192^2: time per sweep of each form
+    n = 8192
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    f_host = W.grf_rhs(n, W.SEED_GRF_8192)
+    per = {}
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+        a = px.alloc_grid(n, tdt)
+        b = px.alloc_grid(n, tdt)
+        f = px.alloc_rhs(n, tdt)
+        src = torch.from_numpy(f_host).cuda()
+        f[:, :n] = src if dt == "f64" else src.float().to(tdt)
+        k, rows, _ = px.autotune(a, b, n, f, ctx)
+        t = time_region(lambda: px.relax_fused(a, b, n, f, h, lam, 64, ctx, tblock=0, resmode=px.RES_NONE),
+                        reps=5, warmup=2)
+        per[dt] = {"s_per_sweep": t / (5 * 64), "k": k, "rows": rows,
+                   "gcell_s": round(n * n * 64 * 5 / t / 1e9, 1)}
+        del a, b, f, src
+        torch.cuda.empty_cache()
+    # refinement step (FP64 residual + update + rounding of r) at 8192^2: one mixed solve
+    # with a budget of one outer step, timed on the host
+    phi = px.alloc_grid(n, torch.float64)
+    f = px.alloc_rhs(n, torch.float64)
+    f[:, :n] = torch.from_numpy(f_host).cuda()
+    for inner, mode in ((64, px.SOLVE_MIXED_F32), (32, px.SOLVE_MIXED_BF16)):
+        phi.zero_()
+        st = px.solve(phi, n, f, h, lam, ctx, mode=mode, rtol=0.0, max_sweeps=inner * 4, inner_sweeps=inner,
+                      raise_on_error=False)
+        per["mixed_" + ("f32" if mode == px.SOLVE_MIXED_F32 else "bf16")] = {
+            "s_per_sweep_incl_refine": st.seconds / st.sweeps, "inner": inner, "outer_steps": st.outer_steps}
+    g = exact.mode_factor(n, 1, 1, OMEGA)
+    floor = 5.6e-10  # FP64 attainable relative residual for this field at 8192^2 (exact solution rounded)
+    tau = max(1e-10, 4 * floor)
+    sweeps = math.log(tau) / math.log(g)
+    t_plain = sweeps * per["f64"]["s_per_sweep"]
+    for key in ("mixed_f32", "mixed_bf16"):
+        per[key]["extrapolated_seconds_to_tau"] = sweeps * per[key]["s_per_sweep_incl_refine"]
+        per[key]["speedup_vs_plain_f64"] = t_plain / per[key]["extrapolated_seconds_to_tau"]
+    per["plain_f64_extrapolated_seconds_to_tau"] = t_plain
+    per["tau_eff"] = tau
+    per["sweeps_to_tau_closed_form"] = sweeps
+    out["per_sweep_8192"] = per
+    log(f"  mixed/8192: {per}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,6 +224,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (the known-size kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--workload", choices=["relax", "mixed"], default="relax",
+                    help="relax: the fused relaxation benchmark (default); mixed: mixed-precision "
+                         "refinement against plain FP64 (time to tolerance)")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=24)
@@ -175,6 +254,17 @@ def main():
     torch.cuda.set_device(0)
     ctx = px.Context(0)
     norms = torch.zeros(2, dtype=torch.float64, device="cuda")
+    if args.workload == "mixed":
+        t0 = time.perf_counter()
+        res = mixed_workload(px, ctx)
+        p8 = res["per_sweep_8192"]
+        print(json.dumps({"metric": METRIC, "workload": "mixed_precision_refinement_grf",
+                          "value": round(p8["mixed_f32"]["speedup_vs_plain_f64"], 3),
+                          "unit": "x time-to-tolerance speedup (mixed FP32 vs plain FP64, 8192^2, extrapolated)",
+                          "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "results": res,
+                          "wall_s": round(time.perf_counter() - t0, 1)}), flush=True)
+        ctx.close()
+        return
 
     d = setup(N, "f64")
     ctx.reserve(N, d["phi0"].stride(0), px.F64)

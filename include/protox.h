@@ -203,6 +203,45 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
              double lambda, const px_solve_opts *opts, px_solve_stats *stats, px_ctx *ctx,
              void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* Batches of independent problems (not in the paper: many Poisson problems */
+/* of uneven sizes solved together).                                        */
+/* ---------------------------------------------------------------------- */
+typedef struct px_problem {
+    void *phi;        /* device, (n+2) x ld: initial iterate in, result out (in place) */
+    const void *f;    /* device, n x ld_f                                              */
+    int n, ld, ld_f;
+    double h, lambda; /* as for px_relax_fused                                         */
+} px_problem;
+
+/*
+ * nsweeps fused sweeps on every problem of the batch (all of element type
+ * dtype and boundary mode bc), in place.  One persistent kernel launch per
+ * tblock sweeps walks the tiles of all problems; intermediate iterates live in
+ * ctx-owned memory.  norms (device, 2*nprob doubles) receives each problem's
+ * {max|r|, sum r^2} of its final iterate when resmode is PX_RES_FINAL (other
+ * modes: no norms; norms may be NULL).  probs is a host array.  Every phi and f
+ * must start 16-byte aligned with ld and ld_f multiples of 16 bytes
+ * (PX_EINVAL otherwise); the problems' phi must not overlap (PX_EALIAS).
+ */
+int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps, int tblock, int bc,
+                     int resmode, double *norms, px_ctx *ctx, void *stream);
+
+/*
+ * Solve every problem of the batch to its tolerance with FP64 iterative
+ * refinement around low-precision inner sweeps (opts->mode PX_SOLVE_MIXED_F32
+ * or PX_SOLVE_MIXED_BF16; phi and f are FP64; the arithmetic is that of
+ * px_solve with the same mode, inner_sweeps and tblock, so every problem's
+ * result equals its single-problem solve).  One outer step of the whole batch
+ * is captured once as a hipGraph and replayed; problems that converge are
+ * switched off on the device.  stats: host array of nprob entries (may be
+ * NULL); .seconds is the wall time of the whole batch.  Returns PX_OK when
+ * every problem converged, else the status of the first that did not.
+ * Waits on `stream`.
+ */
+int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *opts, px_solve_stats *stats,
+                     px_ctx *ctx, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

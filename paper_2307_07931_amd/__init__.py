@@ -55,9 +55,15 @@ class _SolveStats(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class _Problem(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_void_p), ("f", ctypes.c_void_p), ("n", ctypes.c_int),
+                ("ld", ctypes.c_int), ("ld_f", ctypes.c_int), ("h", ctypes.c_double),
+                ("lambda_", ctypes.c_double)]
+
+
 EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
            "px_autotune", "px_last_error", "px_version", "px_apply_stencil", "px_residual",
-           "px_jacobi_update", "px_relax_fused", "px_solve")
+           "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched")
 
 _lib = None
 
@@ -87,7 +93,11 @@ def lib() -> ctypes.CDLL:
                            ctypes.POINTER(_SolveStats), P, P]
     L.px_autotune.argtypes = [P, P, I, I, I, P, I, I, P, P, ctypes.POINTER(I), ctypes.POINTER(I),
                               ctypes.POINTER(D)]
-    for nm in ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
+    L.px_relax_batched.argtypes = [ctypes.POINTER(_Problem), I, I, I, I, I, I, P, P, P]
+    L.px_solve_batched.argtypes = [ctypes.POINTER(_Problem), I, ctypes.POINTER(_SolveOpts),
+                                   ctypes.POINTER(_SolveStats), P, P]
+    for nm in ("px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
+               "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
                "px_apply_stencil", "px_residual", "px_jacobi_update", "px_relax_fused", "px_solve"):
         getattr(L, nm).restype = I
     _lib = L
@@ -280,3 +290,45 @@ def solve(phi, n, f, h, lam, ctx: Context, mode=SOLVE_PLAIN, rtol=1e-10, norm=0,
         _check(st)
     return SolveStats(st, s.sweeps, s.outer_steps, s.res_max, s.res_l2, s.rel_res_max, s.rel_res_l2,
                       s.seconds)
+
+
+# ----------------------------------------------------------------- batches --
+
+def _problems(items):
+    """items: sequence of (phi, f, n, h, lam); returns a ctypes array of px_problem."""
+    arr = (_Problem * len(items))()
+    dt = None
+    for k, (phi, f, n, h, lam) in enumerate(items):
+        ld = _ld(phi, n + 2, n + 2, f"phi[{k}]")
+        ldf = _ld(f, n, n, f"f[{k}]")
+        if dt is None:
+            dt = phi.dtype
+        if phi.dtype != dt or f.dtype != dt:
+            raise TypeError("every phi and f of a batch must share one dtype")
+        arr[k] = _Problem(phi.data_ptr(), f.data_ptr(), n, ld, ldf, float(h), float(lam))
+    return arr, dt
+
+
+def relax_batched(items, nsweeps, ctx: Context, tblock=0, bc=BC_DIRICHLET0, resmode=RES_FINAL,
+                  norms=None, stream=None):
+    """nsweeps fused sweeps on every (phi, f, n, h, lam) of the batch, in place; norms
+    (float64 device tensor of 2*len(items)) gets each problem's final {max|r|, sum r^2}."""
+    arr, dt = _problems(items)
+    _check(lib().px_relax_batched(arr, len(items), _DTYPE_CODE[dt], int(nsweeps), int(tblock), int(bc),
+                                  int(resmode), _ptr(norms), ctx.handle, _stream_handle(stream)))
+
+
+def solve_batched(items, ctx: Context, mode=SOLVE_MIXED_F32, rtol=1e-8, norm=0, max_sweeps=10 ** 9,
+                  inner_sweeps=0, tblock=0, bc=BC_DIRICHLET0, stream=None, raise_on_error=True):
+    """FP64-refined mixed-precision solve of every (phi, f, n, h, lam) (float64) in place;
+    returns (status, [SolveStats per problem])."""
+    arr, _ = _problems(items)
+    o = _SolveOpts(int(mode), int(norm), float(rtol), int(max_sweeps), 0, int(inner_sweeps),
+                   int(tblock), int(bc))
+    st = (_SolveStats * len(items))()
+    status = lib().px_solve_batched(arr, len(items), ctypes.byref(o), st, ctx.handle,
+                                    _stream_handle(stream))
+    if status != OK and raise_on_error:
+        _check(status)
+    return status, [SolveStats(status, x.sweeps, x.outer_steps, x.res_max, x.res_l2, x.rel_res_max,
+                               x.rel_res_l2, x.seconds) for x in st]

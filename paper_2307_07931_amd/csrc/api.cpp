@@ -13,6 +13,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 using namespace px;
 
@@ -38,6 +40,8 @@ struct px_ctx {
     // mixed precision: FP64 second grid, two low-precision ghosted grids, low r
     void *mix = nullptr;
     size_t mix_bytes = 0;
+    // batched calls
+    BatchWork *batch = nullptr;
 };
 
 namespace {
@@ -275,6 +279,11 @@ int px_ctx_destroy(px_ctx *ctx)
         if (ctx->norms_dev) (void)hipFree(ctx->norms_dev);
         if (ctx->norms_host) (void)hipHostFree(ctx->norms_host);
         if (ctx->mix) (void)hipFree(ctx->mix);
+    }
+    if (ctx->batch) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        delete ctx->batch;
     }
     delete ctx;
     return PX_OK;
@@ -610,6 +619,100 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
     S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = S;
     return result;
+}
+
+static int check_batch(const px_problem *probs, int nprob, int dtype, std::vector<BatchProblem> &out)
+{
+    if (!probs) return fail(PX_EINVAL, "probs is NULL");
+    if (nprob < 1 || nprob > (1 << 20)) return fail(PX_EINVAL, "nprob = %d outside [1, 2^20]", nprob);
+    if (!valid_dtype(dtype)) return fail(PX_EINVAL, "unknown dtype %d", dtype);
+    const size_t es = (size_t)elem_size(dtype);
+    out.resize(nprob);
+    std::vector<std::pair<uintptr_t, uintptr_t>> ranges(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        const px_problem &q = probs[p];
+        int st = check_n_ld(q.n, q.ld, dtype);
+        if (!st) st = check_ptr(q.phi, dtype, "phi");
+        if (!st) st = check_flat(q.f, q.n, q.ld_f, dtype, "f");
+        if (!st) st = check_pos(q.h, "h");
+        if (!st) st = check_pos(q.lambda, "lambda");
+        if (st) return fail(st, "problem %d: %s", p, px_last_error());
+        if (reinterpret_cast<uintptr_t>(q.phi) % 16 || reinterpret_cast<uintptr_t>(q.f) % 16 ||
+            ((size_t)q.ld * es) % 16 || ((size_t)q.ld_f * es) % 16)
+            return fail(PX_EINVAL, "problem %d: rows of phi and f must start on 16-byte boundaries", p);
+        const size_t gb = grid_bytes(q.n, q.ld, dtype);
+        if (overlap(q.f, flat_bytes(q.n, q.ld_f, dtype), q.phi, gb))
+            return fail(PX_EALIAS, "problem %d: phi overlaps f", p);
+        ranges[p] = {reinterpret_cast<uintptr_t>(q.phi), reinterpret_cast<uintptr_t>(q.phi) + gb};
+        out[p] = BatchProblem{q.phi, q.f, q.n, q.ld, q.ld_f, q.h, q.lambda};
+    }
+    std::sort(ranges.begin(), ranges.end());
+    for (int p = 1; p < nprob; ++p)
+        if (ranges[p].first < ranges[p - 1].second) return fail(PX_EALIAS, "two problems' phi overlap");
+    return PX_OK;
+}
+
+int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps, int tblock, int bc,
+                     int resmode, double *norms, px_ctx *ctx, void *stream)
+{
+    std::vector<BatchProblem> bp;
+    int st = check_batch(probs, nprob, dtype, bp);
+    if (st) return st;
+    if (nsweeps < 1) return fail(PX_EINVAL, "nsweeps = %d < 1", nsweeps);
+    if (tblock < 0 || tblock > 8) return fail(PX_EINVAL, "tblock = %d outside [0, 8]", tblock);
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (resmode < RES_NONE || resmode > RES_FINAL) return fail(PX_EINVAL, "unknown resmode %d", resmode);
+    if (resmode == RES_LAGGED) return fail(PX_EUNSUPPORTED, "batched relaxation reports FINAL norms only");
+    if (resmode == RES_FINAL && !norms) return fail(PX_EINVAL, "norms is NULL");
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = set_device(ctx))) return st;
+    if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+    if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
+    char err[256] = "";
+    st = batch_relax(*ctx->batch, dtype, bp.data(), nprob, nsweeps, tblock ? tblock : 8, bc, resmode, norms,
+                     ctx->tile_rows, (hipStream_t)stream, err, sizeof err);
+    return st ? fail(st, "%s", err) : PX_OK;
+}
+
+int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *o, px_solve_stats *stats,
+                     px_ctx *ctx, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<BatchProblem> bp;
+    int st = check_batch(probs, nprob, F64, bp);
+    if (st) return st;
+    if (!o) return fail(PX_EINVAL, "opts is NULL");
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if (o->mode == PX_SOLVE_PLAIN) return fail(PX_EUNSUPPORTED, "batched solves refine around FP32/BF16 sweeps");
+    if (o->mode != PX_SOLVE_MIXED_F32 && o->mode != PX_SOLVE_MIXED_BF16) return fail(PX_EINVAL, "unknown mode");
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(PX_EINVAL, "rtol must be finite and >= 0");
+    if (o->norm != 0 && o->norm != 1) return fail(PX_EINVAL, "norm must be 0 (max) or 1 (L2)");
+    if (o->max_sweeps < 0) return fail(PX_EINVAL, "max_sweeps < 0");
+    if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
+    if (!valid_bc(o->bc)) return fail(PX_EINVAL, "unknown bc %d", o->bc);
+    const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : 32;
+    const int k = std::min(o->tblock ? o->tblock : 8, inner);
+    if ((st = set_device(ctx))) return st;
+    if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+    if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
+    std::vector<BatchStat> bs(nprob);
+    char err[256] = "";
+    const int lowp = o->mode == PX_SOLVE_MIXED_F32 ? F32 : BF16;
+    st = batch_solve(*ctx->batch, lowp, bp.data(), nprob, o->bc, o->rtol, o->norm, o->max_sweeps, inner, k, 8,
+                     bs.data(), (hipStream_t)stream, err, sizeof err);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+        for (int p = 0; p < nprob; ++p) {
+            px_solve_stats &S = stats[p];
+            S.sweeps = bs[p].sweeps;
+            S.outer_steps = bs[p].steps;
+            S.res_max = bs[p].res_max;
+            S.res_l2 = bs[p].res_l2;
+            S.rel_res_max = bs[p].rel_res_max;
+            S.rel_res_l2 = bs[p].rel_res_l2;
+            S.seconds = secs;
+        }
+    return st ? fail(st, "%s", err) : PX_OK;
 }
 
 }  // extern "C"

@@ -102,4 +102,31 @@ hipError_t refine_launch(int lowp, const double *phi_in, const void *delta, int 
                          void *r_low, int ld_r, Partials part, hipStream_t s);
 hipError_t zero_grid_launch(int dtype, void *p, int n, int ld, hipStream_t s);
 
+// ---- batches of independent problems (batched.hip)
+struct BatchProblem {
+    void *phi;        // (n+2) x ld, in place
+    const void *f;    // n x ld_f
+    int n, ld, ld_f;
+    double h, lambda;
+};
+struct BatchStat {
+    int state;        // 0 converged, -1 sweep budget, -2 non-finite, -3 diverged
+    long long steps, sweeps;
+    double res_max, res_l2, rel_res_max, rel_res_l2;
+};
+// Device memory, work stream and graph of batched calls, owned by a context.
+struct BatchWork {
+    void *mem = nullptr;
+    size_t bytes = 0;
+    void *stream = nullptr;
+    void *graph_exec = nullptr;
+    ~BatchWork();
+    hipError_t ensure(size_t need);
+};
+int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int nsweeps, int k, int bc,
+                int resmode, double *norms, int forced_rows, hipStream_t s, char *err, size_t errlen);
+int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, int bc, double rtol,
+                int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, BatchStat *stats,
+                hipStream_t user_stream, char *err, size_t errlen);
+
 }  // namespace px

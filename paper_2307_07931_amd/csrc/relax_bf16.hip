@@ -9,5 +9,10 @@ LaunchFn pick_bf16(int k, int rm, bool vec)
     return vec ? pick_k<bf16, true>(k, rm) : pick_k<bf16, false>(k, rm);
 }
 
+BatchLaunchFn pick_batch_bf16(int k, int rm)
+{
+    return pick_batch_k<bf16>(k, rm);
+}
+
 }  // namespace relax_detail
 }  // namespace px

@@ -9,5 +9,10 @@ LaunchFn pick_f64(int k, int rm, bool vec)
     return vec ? pick_k<double, true>(k, rm) : pick_k<double, false>(k, rm);
 }
 
+BatchLaunchFn pick_batch_f64(int k, int rm)
+{
+    return pick_batch_k<double>(k, rm);
+}
+
 }  // namespace relax_detail
 }  // namespace px

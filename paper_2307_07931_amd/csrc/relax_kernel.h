@@ -480,57 +480,110 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 
 }
 
+// One wave tile of one problem: geometry, interior/edge dispatch, streaming loop.
 template <typename T, int V, int K, int RM, int PF, bool VEC>
-__global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const KArgs p)
+__device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lane, unsigned long long &rmax,
+                                               double &rsum)
 {
-    using E = Elem<T>;
-    using A = typename E::A;
     constexpr int NL = K + (RM == RES_FINAL ? 1 : 0);  // pipeline levels
-
-    // XCD-aware block order: block b runs on XCD b % 8; give each XCD a contiguous
-    // run of tiles so neighbouring tiles (shared halo rows/columns) share an L2.
-    const int nb = gridDim.x, b = blockIdx.x;
-    const int nb8 = nb & ~7;
-    const int lb = (b < nb8) ? ((b & 7) * (nb8 >> 3) + (b >> 3)) : b;
-    // the wave index is uniform across the wave; say so, so every tile quantity and
-    // every row descriptor lives in scalar registers
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int tile = lb * WAVES_PER_BLOCK + wave;
-    if (tile >= p.ntiles) return;  // wave-uniform; waves never synchronise
-    const int lane = threadIdx.x & (WAVE - 1);
-
     const int n = p.n;
     const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
     const int oc0 = p.col_origin + tx * p.stride;  // output columns [oc0, oc1)
     const int oc1 = min(oc0 + p.stride, n + 2);
-    const int mc = oc0 - p.halo + lane * V;        // first column held by this lane
+    const int c0 = oc0 - p.halo;                   // first column held by the wave
+    const int mc = c0 + lane * V;                  // first column held by this lane
     const int y0 = ty * p.rows, y1 = min(y0 + p.rows, n + 2);
     // tiles whose outputs avoid columns 0, 1, n, n+1 store whole vectors
     const bool whole = oc0 >= V && oc1 <= n;
     // interior tile: loaded columns and needed rows all inside [1, n]
-    const bool interior = (mc - lane * V) >= 1 && (mc - lane * V) + WAVE * V - 1 <= n &&
-                          y0 - NL >= 1 && y1 + NL - 1 <= n;
+    const bool interior = c0 >= 1 && c0 + WAVE * V - 1 <= n && y0 - NL >= 1 && y1 + NL - 1 <= n;
     const Tile tl{n, oc0, oc1, mc, y0, y1, whole};
-    unsigned long long rmax = 0;
-    double rsum = 0.0;
     if (interior)
         run_tile<T, V, K, RM, PF, VEC, false>(p, tl, rmax, rsum);
     else
         run_tile<T, V, K, RM, PF, VEC, true>(p, tl, rmax, rsum);
+}
 
-
-    if (RM != RES_NONE) {
+// Wave reduction of the partial norms in a fixed order (result in every lane).
+__device__ __forceinline__ void wave_reduce_norms(unsigned long long &rmax, double &rsum, int lane)
+{
 #pragma unroll
-        for (int off = WAVE / 2; off > 0; off >>= 1) {
-            const unsigned long long om = __shfl_xor(rmax, off, WAVE);
-            const double os = __shfl_xor(rsum, off, WAVE);
-            rmax = om > rmax ? om : rmax;
-            // fixed pairing: the lower lane's value always comes first
-            rsum = (lane & off) ? (os + rsum) : (rsum + os);
-        }
+    for (int off = WAVE / 2; off > 0; off >>= 1) {
+        const unsigned long long om = __shfl_xor(rmax, off, WAVE);
+        const double os = __shfl_xor(rsum, off, WAVE);
+        rmax = om > rmax ? om : rmax;
+        // fixed pairing: the lower lane's value always comes first
+        rsum = (lane & off) ? (os + rsum) : (rsum + os);
+    }
+}
+
+// XCD-aware block order: block b runs on XCD b % 8; give each XCD a contiguous run
+// of tiles so neighbouring tiles (shared halo rows/columns) share an L2.
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int nb8 = nb & ~7;
+    return (b < nb8) ? ((b & 7) * (nb8 >> 3) + (b >> 3)) : b;
+}
+
+template <typename T, int V, int K, int RM, int PF, bool VEC>
+__global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const KArgs p)
+{
+    // the wave index is uniform across the wave; say so, so every tile quantity and
+    // every row descriptor lives in scalar registers
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int tile = xcd_block() * WAVES_PER_BLOCK + wave;
+    if (tile >= p.ntiles) return;  // wave-uniform; waves never synchronise
+    const int lane = threadIdx.x & (WAVE - 1);
+    unsigned long long rmax = 0;
+    double rsum = 0.0;
+    relax_one_tile<T, V, K, RM, PF, VEC>(p, tile, lane, rmax, rsum);
+    if (RM != RES_NONE) {
+        wave_reduce_norms(rmax, rsum, lane);
         if (lane == 0) {
             p.pmax[tile] = rmax;
             p.psum[tile] = rsum;
+        }
+    }
+}
+
+// Batch of independent problems in one persistent launch: the tiles of all
+// problems form one list (tile_off = prefix sums of per-problem tile counts) and
+// every wave walks it with a stride of the whole grid.  Problems whose `active`
+// flag is not 1 are skipped, so a captured launch sequence stays valid while
+// problems finish at different times.  Partial norms go to one slot per item.
+struct BatchArgs {
+    const KArgs *probs;   // per-problem launch arguments (device array)
+    const int *tile_off;  // nprob + 1 entries
+    const int *active;    // per-problem flag, NULL = all active
+    int nprob, total;
+    unsigned long long *pmax;
+    double *psum;
+};
+
+template <typename T, int V, int K, int RM, int PF, bool VEC>
+__global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_batch_kernel(const BatchArgs b)
+{
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int stride = gridDim.x * WAVES_PER_BLOCK;
+    for (int item = xcd_block() * WAVES_PER_BLOCK + wave; item < b.total; item += stride) {
+        int lo = 0, hi = b.nprob;  // tile_off[lo] <= item < tile_off[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (b.tile_off[mid] <= item) lo = mid; else hi = mid;
+        }
+        if (b.active && b.active[lo] != 1) continue;
+        const KArgs p = b.probs[lo];
+        unsigned long long rmax = 0;
+        double rsum = 0.0;
+        relax_one_tile<T, V, K, RM, PF, VEC>(p, item - b.tile_off[lo], lane, rmax, rsum);
+        if (RM != RES_NONE) {
+            wave_reduce_norms(rmax, rsum, lane);
+            if (lane == 0) {
+                b.pmax[item] = rmax;
+                b.psum[item] = rsum;
+            }
         }
     }
 }
@@ -572,7 +625,51 @@ LaunchFn pick_k(int k, int rm)
 
 
 
+using BatchLaunchFn = hipError_t (*)(const BatchArgs &, hipStream_t);
+
+// Persistent grid: as many blocks as fit on the device at once.
+template <typename T, int K, int RM>
+hipError_t launch_batch_inst(const BatchArgs &ba, hipStream_t s)
+{
+    auto kern = relax_batch_kernel<T, VecOf<T>::V, K, RM, PREFETCH, true>;
+    int per_cu = 0, dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kern),
+                                                          WAVE * WAVES_PER_BLOCK, 0);
+    if (e != hipSuccess) return e;
+    const int blocks = std::max(1, std::min(per_cu * cus, (ba.total + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK));
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(WAVE * WAVES_PER_BLOCK), 0, s, ba);
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+BatchLaunchFn pick_batch_rm(int rm)
+{
+    return rm == RES_NONE ? &launch_batch_inst<T, K, RES_NONE> : &launch_batch_inst<T, K, RES_FINAL>;
+}
+
+template <typename T>
+BatchLaunchFn pick_batch_k(int k, int rm)
+{
+    switch (k) {
+    case 1: return pick_batch_rm<T, 1>(rm);
+    case 2: return pick_batch_rm<T, 2>(rm);
+    case 3: return pick_batch_rm<T, 3>(rm);
+    case 4: return pick_batch_rm<T, 4>(rm);
+    case 5: return pick_batch_rm<T, 5>(rm);
+    case 6: return pick_batch_rm<T, 6>(rm);
+    case 7: return pick_batch_rm<T, 7>(rm);
+    case 8: return pick_batch_rm<T, 8>(rm);
+    default: return nullptr;
+    }
+}
+
 // Per-element-type launcher tables, each compiled in its own translation unit.
+BatchLaunchFn pick_batch_f64(int k, int rm);
+BatchLaunchFn pick_batch_f32(int k, int rm);
+BatchLaunchFn pick_batch_bf16(int k, int rm);
 LaunchFn pick_f64(int k, int rm, bool vec);
 LaunchFn pick_f32(int k, int rm, bool vec);
 LaunchFn pick_bf16(int k, int rm, bool vec);

@@ -167,3 +167,35 @@ def test_python_binding_rejects_bad_layouts():
         px._ld(phi, 9, 10, "phi")
     with pytest.raises(TypeError):
         px.dtype_code(torch.zeros(1, dtype=torch.int32))
+
+
+def test_batched_validation(ctx):
+    L = px.lib()
+    P = ctypes.c_void_p
+    probs = (px._Problem * 2)(px._Problem(FAKE, FAKE2, 8, 16, 8, 0.125, 1e-3),
+                              px._Problem(FAKE2 * 2, FAKE2 * 3, 8, 16, 8, 0.125, 1e-3))
+    ok = dict(nprob=2, dtype=px.F64, nsweeps=4, tblock=2, bc=0, resmode=0)
+
+    def relax(**kw):
+        a = dict(ok)
+        a.update(kw)
+        return L.px_relax_batched(kw.get("probs", probs), a["nprob"], a["dtype"], a["nsweeps"], a["tblock"],
+                                  a["bc"], a["resmode"], None, ctx, None)
+
+    assert relax(nprob=0) == px.EINVAL
+    assert relax(nsweeps=0) == px.EINVAL
+    assert relax(tblock=9) == px.EINVAL
+    assert relax(resmode=2) == px.EINVAL            # FINAL needs norms
+    assert relax(resmode=1) == px.EUNSUPPORTED      # lagged norms are not reported for batches
+    bad = (px._Problem * 2)(probs[0], px._Problem(FAKE + 8, FAKE2 * 3, 8, 16, 8, 0.125, 1e-3))
+    assert relax(probs=bad) == px.EINVAL           # not 16-byte aligned
+    over = (px._Problem * 2)(probs[0], px._Problem(FAKE + 256, FAKE2 * 3, 8, 16, 8, 0.125, 1e-3))
+    assert relax(probs=over) == px.EALIAS          # two problems share memory
+    oddld = (px._Problem * 1)(px._Problem(FAKE, FAKE2, 8, 11, 8, 0.125, 1e-3))
+    assert relax(probs=oddld, nprob=1) == px.EINVAL
+    st = (px._SolveStats * 2)()
+    o = px._SolveOpts(px.SOLVE_PLAIN, 0, 1e-8, 100, 0, 8, 0, 0)
+    assert L.px_solve_batched(probs, 2, ctypes.byref(o), st, ctx, None) == px.EUNSUPPORTED
+    o = px._SolveOpts(px.SOLVE_MIXED_F32, 3, 1e-8, 100, 0, 8, 0, 0)
+    assert L.px_solve_batched(probs, 2, ctypes.byref(o), st, ctx, None) == px.EINVAL
+    assert L.px_solve_batched(probs, 2, None, st, ctx, None) == px.EINVAL
