@@ -118,3 +118,14 @@ def pad_rows(f: np.ndarray, ld_f: int, dtype=np.float64) -> np.ndarray:
     out = np.zeros((n, ld_f), dtype=dtype)
     out[:, :f.shape[1]] = f
     return out
+
+
+NET_SHAPES = ((32, 1, 3, 3), (32, 32, 3, 3), (32, 32, 3, 3), (1, 32, 3, 3))
+
+
+def net_initial_weights(seed: int) -> np.ndarray:
+    """Initial weights of the 4-layer 3x3 correction network (19008 numbers, layers in
+    order, each in (out, in, 3, 3) C order): He-normal, std sqrt(2 / (9 * in)), from
+    PCG64(seed)."""
+    g = rng(seed)
+    return np.concatenate([(g.standard_normal(s) * np.sqrt(2.0 / (s[1] * 9))).ravel() for s in NET_SHAPES])
