@@ -242,6 +242,109 @@ int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps,
 int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *opts, px_solve_stats *stats,
                      px_ctx *ctx, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* Learned correction network (not in the paper: a small convolutional     */
+/* network that maps a residual to a correction inside a refinement loop). */
+/* ---------------------------------------------------------------------- */
+/*
+ * Architecture: x -> conv3x3(1->32) -> ReLU -> conv3x3(32->32) -> ReLU ->
+ * conv3x3(32->32) -> ReLU -> conv3x3(32->1) -> y; no bias; zero padding (every
+ * activation is 0 outside the image).  Weights: PX_NET_NPARAM FP32 numbers, the
+ * four layers in order, each in (out, in, 3, 3) C order.  Arithmetic: the input,
+ * the weights and every hidden activation are rounded to bfloat16 (nearest, ties
+ * to even); sums accumulate in FP32 (the 32->32 layers on the matrix cores).
+ * Images: `batch` images of H x W pixels, row-major, FP32 unless stated.
+ */
+#define PX_NET_NPARAM 19008
+
+typedef struct px_net px_net;
+
+typedef enum px_loss {
+    PX_LOSS_MSE = 0,    /* mean over pixels of (y - t)^2                                  */
+    PX_LOSS_ENERGY = 1  /* mean over pixels of (y - t) K (y - t), K = 4 I - (4 neighbours),
+                           odd reflection at the image edges (the negated 5-point stencil
+                           under PX_BC_DIRICHLET0): the energy norm of the error           */
+} px_loss;
+
+/* Network on `device` with the given initial weights (host array of
+ * PX_NET_NPARAM); optimiser state (Adam moments, step count) starts at zero. */
+int px_net_create(int device, const float *weights, px_net **out);
+int px_net_destroy(px_net *net);
+/* Replace the weights (host array) and reset the optimiser state.  Waits. */
+int px_net_set_weights(px_net *net, const float *weights);
+/* Copy the FP32 master weights to a host array of PX_NET_NPARAM.  Waits. */
+int px_net_get_weights(px_net *net, float *weights);
+
+/*
+ * y = N(x * x_scale) for `batch` images.  x: device, x_dtype PX_F64 or PX_F32,
+ * image b row i at x + (b*H + i)*ldx (ldx >= W); y: device FP32, rows of ldy >= W.
+ * The scaled input is rounded to bfloat16 as the first layer's input.
+ */
+int px_net_forward(px_net *net, const void *x, int x_dtype, int ldx, int batch, int H, int W,
+                   double x_scale, float *y, int ldy, void *stream);
+
+/*
+ * One training evaluation on inputs x and targets t (device, FP32, compact
+ * batch x H x W): forward pass, loss (px_loss), backward pass.  The gradient with
+ * respect to the FP32 weights is kept in the network for px_net_adam and, when
+ * grad is not NULL, copied to grad (device, PX_NET_NPARAM floats).  When loss_out
+ * is not NULL (device, one double) it receives the loss.  The loss and every
+ * gradient are reduced in a fixed order: results are reproducible bit for bit.
+ */
+int px_net_loss_grad(px_net *net, const float *x, const float *t, int batch, int H, int W, int loss,
+                     double *loss_out, float *grad, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) with the
+ * gradient of the last px_net_loss_grad call, then re-rounds the bfloat16 copies. */
+int px_net_adam(px_net *net, float lr, void *stream);
+
+/* Copy the hidden activation of layer 1, 2 or 3 of the last forward pass
+ * (bfloat16 bit patterns, channels last: batch*H*W*32 values) to out (device). */
+int px_net_activation(px_net *net, int layer, uint16_t *out, void *stream);
+
+/*
+ * A training pair from an iterate phi ((n+2) x ld FP64, device) of the
+ * homogeneous problem L phi = 0 under PX_BC_DIRICHLET0, whose exact solution is
+ * 0: error e = -phi and residual r = -L phi.  Writes x = r / rms(r) and the target
+ * t = e / rms(e) (PX_LOSS_MSE) or t = e / sqrt(mean(e K e)) (PX_LOSS_ENERGY), as
+ * compact n x n FP32 (device).  Scale factors 1/h^2 cancel, so h is not needed.
+ * A field that is identically zero is written as zeros.  Uses ctx scratch.
+ */
+int px_net_make_pair(const double *phi, int n, int ld, int loss, float *x, float *t, px_ctx *ctx,
+                     void *stream);
+
+typedef struct px_learned_opts {
+    int norm;             /* 0: stop on max-norm, 1: on the L2 norm                    */
+    double rtol;          /* stop when ||r|| <= rtol * ||f|| (same norm)               */
+    int64_t max_sweeps;   /* budget of relaxation sweeps                               */
+    int smooth_sweeps;    /* plain sweeps after each correction (>= 1)                 */
+    int tblock;           /* sweeps per launch, 0 = default                            */
+    int use_net;          /* 1: correction direction N(r / rms(r)); 0: direction r (the
+                             same loop without the network)                            */
+} px_learned_opts;
+
+typedef struct px_learned_stats {
+    px_solve_stats base;  /* sweeps, outer_steps (= steps of the loop), norms, time    */
+    int64_t corrections;  /* correction steps kept                                     */
+    int64_t rejected;     /* correction steps undone by the judge                      */
+    int fell_back;        /* 1 when the solve finished with plain relaxation only      */
+} px_learned_stats;
+
+/*
+ * Solve L phi = f (FP64 phi and f, PX_BC_DIRICHLET0) by a refinement loop.  Each
+ * step: r = f - L phi in FP64; a direction d (network output or r); the step
+ * length a = <r, d> / <d, L d> that minimises the energy norm of the error along
+ * d; phi += a d (FP64); then smooth_sweeps fused relaxation sweeps.  Plain
+ * relaxation judges the step: if the residual L2 norm after it is not below the
+ * one before, or not finite, the step is undone and the solve continues with plain
+ * relaxation alone (the loop of px_solve PX_SOLVE_PLAIN with check_every =
+ * smooth_sweeps).  Stopping rules and return codes as px_solve.  Waits on
+ * `stream` every step.  net may be NULL when use_net is 0.  stats may be NULL.
+ */
+int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double h, double lambda,
+                     px_net *net, const px_learned_opts *opts, px_learned_stats *stats, px_ctx *ctx,
+                     void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,8 @@ Weights in C order: W1 (32,1,3,3), W2 (32,32,3,3), W3 (32,32,3,3), W4 (1,32,3,3)
 Precision model of the GPU kernels (BF16 in, FP32 accumulate): weights, the input
 and every hidden activation are rounded to bfloat16 before they are used; sums are
 taken here in FP64.  `bf16=False` switches all rounding off (pure FP64 network, used
-for finite-difference pins).  Loss: mean squared error over all output pixels.
+for finite-difference pins).  Losses: mean squared error, or the mean energy
+(y - t) K (y - t) with K the negated 5-point stencil under odd reflection.
 """
 from __future__ import annotations
 
@@ -100,12 +101,38 @@ def forward(w_flat: np.ndarray, x: np.ndarray, bf16: bool = True):
     return y, dict(a0=a0, a1=a1, a2=a2, a3=a3, W=(W1, W2, W3, W4), bf16=bf16)
 
 
-def loss(y: np.ndarray, target: np.ndarray) -> float:
-    return float(np.mean((y - target) ** 2))
+def energy_operator(d: np.ndarray) -> np.ndarray:
+    """K d per image of d (B, H, W): 4 d(i,j) minus its four neighbours, where a neighbour
+    outside the image is taken as -d(i,j) (odd reflection across the edge, the
+    homogeneous Dirichlet ghost).  K is the negated 5-point stencil: symmetric positive
+    definite, so d K d is the (unscaled) energy norm of d."""
+    d = np.asarray(d, dtype=np.float64)
+    g = np.zeros((d.shape[0], d.shape[1] + 2, d.shape[2] + 2))
+    g[:, 1:-1, 1:-1] = d
+    g[:, 0, 1:-1] = -d[:, 0, :]
+    g[:, -1, 1:-1] = -d[:, -1, :]
+    g[:, 1:-1, 0] = -d[:, :, 0]
+    g[:, 1:-1, -1] = -d[:, :, -1]
+    return 4.0 * d - (g[:, :-2, 1:-1] + g[:, 2:, 1:-1] + g[:, 1:-1, :-2] + g[:, 1:-1, 2:])
 
 
-def backward(cache, y: np.ndarray, target: np.ndarray):
-    """Gradient of the mean squared error with respect to the flat weights.
+def loss(y: np.ndarray, target: np.ndarray, kind: str = "mse") -> float:
+    """Mean over pixels of (y - t)^2 ("mse") or of (y - t) K (y - t) ("energy")."""
+    d = np.asarray(y, dtype=np.float64) - target
+    if kind == "energy":
+        return float(np.mean(d * energy_operator(d)))
+    return float(np.mean(d * d))
+
+
+def loss_grad_y(y: np.ndarray, target: np.ndarray, kind: str = "mse") -> np.ndarray:
+    """Derivative of `loss` with respect to y: 2 (y - t) / N, or 2 K (y - t) / N (K is
+    symmetric)."""
+    d = np.asarray(y, dtype=np.float64) - target
+    return (2.0 / d.size) * (energy_operator(d) if kind == "energy" else d)
+
+
+def backward(cache, y: np.ndarray, target: np.ndarray, kind: str = "mse"):
+    """Gradient of the loss (`kind` as in `loss`) with respect to the flat weights.
 
     Mirrors the GPU's rounding points when the forward pass ran with bf16=True: the
     gradients entering each 32-channel convolution (dz3, dz2, and dz1) are rounded to
@@ -113,8 +140,7 @@ def backward(cache, y: np.ndarray, target: np.ndarray):
     rnd = bf16_round if cache["bf16"] else (lambda v: v)
     W1, W2, W3, W4 = cache["W"]
     a0, a1, a2, a3 = cache["a0"], cache["a1"], cache["a2"], cache["a3"]
-    dy = (2.0 / y.size) * (y - target)
-    dy4 = dy[..., None]
+    dy4 = loss_grad_y(y, target, kind)[..., None]
     dW4 = conv3x3_weight_grad(a3, dy4)
     dz3 = rnd(conv3x3_input_grad(dy4, W4) * (a3 > 0))
     dW3 = conv3x3_weight_grad(a2, dz3)

@@ -55,6 +55,16 @@ class _SolveStats(ctypes.Structure):
                 ("seconds", ctypes.c_double)]
 
 
+class _LearnedOpts(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_int), ("rtol", ctypes.c_double), ("max_sweeps", ctypes.c_int64),
+                ("smooth_sweeps", ctypes.c_int), ("tblock", ctypes.c_int), ("use_net", ctypes.c_int)]
+
+
+class _LearnedStats(ctypes.Structure):
+    _fields_ = [("base", _SolveStats), ("corrections", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("fell_back", ctypes.c_int)]
+
+
 class _Problem(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_void_p), ("f", ctypes.c_void_p), ("n", ctypes.c_int),
                 ("ld", ctypes.c_int), ("ld_f", ctypes.c_int), ("h", ctypes.c_double),
@@ -63,7 +73,10 @@ class _Problem(ctypes.Structure):
 
 EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
            "px_autotune", "px_last_error", "px_version", "px_apply_stencil", "px_residual",
-           "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched")
+           "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched",
+           "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
+           "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
+           "px_net_make_pair", "px_solve_learned")
 
 _lib = None
 
@@ -96,7 +109,22 @@ def lib() -> ctypes.CDLL:
     L.px_relax_batched.argtypes = [ctypes.POINTER(_Problem), I, I, I, I, I, I, P, P, P]
     L.px_solve_batched.argtypes = [ctypes.POINTER(_Problem), I, ctypes.POINTER(_SolveOpts),
                                    ctypes.POINTER(_SolveStats), P, P]
-    for nm in ("px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
+    F = ctypes.POINTER(ctypes.c_float)
+    L.px_net_create.argtypes = [I, F, ctypes.POINTER(P)]
+    L.px_net_destroy.argtypes = [P]
+    L.px_net_set_weights.argtypes = [P, F]
+    L.px_net_get_weights.argtypes = [P, F]
+    L.px_net_forward.argtypes = [P, P, I, I, I, I, I, D, P, I, P]
+    L.px_net_loss_grad.argtypes = [P, P, P, I, I, I, I, P, P, P]
+    L.px_net_adam.argtypes = [P, ctypes.c_float, P]
+    L.px_net_activation.argtypes = [P, I, P, P]
+    L.px_net_make_pair.argtypes = [P, I, I, I, P, P, P, P]
+    L.px_solve_learned.argtypes = [P, I, I, P, I, D, D, P, ctypes.POINTER(_LearnedOpts),
+                                   ctypes.POINTER(_LearnedStats), P, P]
+    for nm in ("px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
+               "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
+               "px_net_make_pair", "px_solve_learned",
+               "px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
                "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
                "px_apply_stencil", "px_residual", "px_jacobi_update", "px_relax_fused", "px_solve"):
         getattr(L, nm).restype = I
@@ -332,3 +360,131 @@ def solve_batched(items, ctx: Context, mode=SOLVE_MIXED_F32, rtol=1e-8, norm=0, 
         _check(status)
     return status, [SolveStats(status, x.sweeps, x.outer_steps, x.res_max, x.res_l2, x.rel_res_max,
                                x.rel_res_l2, x.seconds) for x in st]
+
+
+# ---------------------------------------------------- learned correction --
+
+NET_NPARAM = 19008
+LOSS_MSE, LOSS_ENERGY = 0, 1
+
+
+def _host_f32(w):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(w, dtype=np.float32).ravel())
+    if a.size != NET_NPARAM:
+        raise ValueError(f"expected {NET_NPARAM} weights, got {a.size}")
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Net:
+    """Owns a px_net: the 4-layer 3x3 correction network, its FP32 master weights,
+    BF16 copies, Adam state and activation workspace on one device."""
+
+    def __init__(self, weights, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        a, p = _host_f32(weights)
+        h = ctypes.c_void_p()
+        _check(lib().px_net_create(int(device), p, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def set_weights(self, weights):
+        a, p = _host_f32(weights)
+        _check(lib().px_net_set_weights(self._h, p))
+
+    def get_weights(self):
+        import numpy as np
+        a = np.zeros(NET_NPARAM, dtype=np.float32)
+        _check(lib().px_net_get_weights(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return a
+
+    def forward(self, x, y, x_scale=1.0, stream=None):
+        """y = N(x * x_scale); x: (B, H, ldx) or (H, ldx) float64/float32 with unit column
+        stride (the first W columns used, W = y's width); y: float32 of shape (B, H, >= W)."""
+        x3 = x if x.dim() == 3 else x.unsqueeze(0)
+        y3 = y if y.dim() == 3 else y.unsqueeze(0)
+        B, H, W = y3.shape[0], y3.shape[1], y3.shape[2]
+        if x3.dtype not in (torch.float64, torch.float32) or y3.dtype != torch.float32:
+            raise TypeError("x must be float64 or float32 and y float32")
+        if x3.shape[0] != B or x3.shape[1] != H or x3.stride(2) != 1 or y3.stride(2) != 1:
+            raise ValueError("x and y must have matching batch and rows, unit column stride")
+        ldx, ldy = x3.stride(1), y3.stride(1)
+        if x3.stride(0) != H * ldx or y3.stride(0) != H * ldy:
+            raise ValueError("images must be stored back to back (stride(0) == H * stride(1))")
+        _check(lib().px_net_forward(self._h, _ptr(x3), dtype_code(x3), ldx, B, H, W, float(x_scale),
+                                    _ptr(y3), ldy, _stream_handle(stream)))
+        return y
+
+    def loss_grad(self, x, t, loss=LOSS_MSE, loss_out=None, grad=None, stream=None):
+        """Forward, loss and backward on contiguous float32 (B, H, W) x and targets t; the
+        gradient stays in the network (and is copied to grad if given)."""
+        if x.dtype != torch.float32 or t.dtype != torch.float32 or not x.is_contiguous() \
+                or not t.is_contiguous() or x.shape != t.shape or x.dim() != 3:
+            raise ValueError("x and t must be contiguous float32 tensors of one (B, H, W) shape")
+        B, H, W = x.shape
+        _check(lib().px_net_loss_grad(self._h, _ptr(x), _ptr(t), B, H, W, int(loss), _ptr(loss_out),
+                                      _ptr(grad), _stream_handle(stream)))
+
+    def adam(self, lr, stream=None):
+        _check(lib().px_net_adam(self._h, ctypes.c_float(lr), _stream_handle(stream)))
+
+    def activation(self, layer, out, stream=None):
+        """Copy layer 1..3 of the last forward pass (bfloat16 bits as int16/uint16, shape
+        (pixels, 32)) into out."""
+        _check(lib().px_net_activation(self._h, int(layer), _ptr(out), _stream_handle(stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().px_net_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def make_pair(phi, n, x, t, ctx: Context, loss=LOSS_MSE, stream=None):
+    """Training pair of the homogeneous problem: x = r / rms(r), t = e / rms(e) (or the
+    energy-norm scaling) with e = -phi, r = -L phi; x and t contiguous float32 (n, n)."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    if phi.dtype != torch.float64:
+        raise TypeError("phi must be float64")
+    for a, nm in ((x, "x"), (t, "t")):
+        if a.dtype != torch.float32 or not a.is_contiguous() or a.numel() != n * n:
+            raise ValueError(f"{nm} must be a contiguous float32 tensor of n*n elements")
+    _check(lib().px_net_make_pair(_ptr(phi), n, ld, int(loss), _ptr(x), _ptr(t), ctx.handle,
+                                  _stream_handle(stream)))
+
+
+@dataclass
+class LearnedStats(SolveStats):
+    corrections: int = 0
+    rejected: int = 0
+    fell_back: int = 0
+
+
+def solve_learned(phi, n, f, h, lam, ctx: Context, net: "Net | None" = None, use_net=True, rtol=1e-10,
+                  norm=0, max_sweeps=10 ** 9, smooth_sweeps=16, tblock=0, stream=None,
+                  raise_on_error=True) -> LearnedStats:
+    """Refinement loop with network (or residual) directions, energy-optimal steps, plain
+    smoothing sweeps and the plain-relaxation judge; float64 phi and f, in place."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    ldf = _ld(f, n, n, "f")
+    o = _LearnedOpts(int(norm), float(rtol), int(max_sweeps), int(smooth_sweeps), int(tblock),
+                     1 if use_net else 0)
+    s = _LearnedStats()
+    st = lib().px_solve_learned(_ptr(phi), n, ld, _ptr(f), ldf, float(h), float(lam),
+                                net.handle if net is not None else ctypes.c_void_p(0), ctypes.byref(o),
+                                ctypes.byref(s), ctx.handle, _stream_handle(stream))
+    if st != OK and raise_on_error:
+        _check(st)
+    b = s.base
+    return LearnedStats(st, b.sweeps, b.outer_steps, b.res_max, b.res_l2, b.rel_res_max, b.rel_res_l2,
+                        b.seconds, s.corrections, s.rejected, s.fell_back)

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libprotox.so")
 SOURCES = ["relax_f64.hip", "relax_f32.hip", "relax_bf16.hip", "relax.hip", "pointwise.hip", "batched.hip",
-           "api.cpp"]
+           "net.hip", "api.cpp"]
 HEADERS = ["px_internal.h", "relax_kernel.h"]
 
 ARCH = "gfx950"
@@ -57,7 +57,7 @@ def build(verbose: bool = False, extra_flags=(), out: str = LIB, build_dir: str 
     """Compile all sources and link the library (default: libprotox.so next to this
     file); extra_flags go to every compile (e.g. -DPX_PREFETCH=2 for tuning builds)."""
     os.makedirs(build_dir, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose, tuple(extra_flags), build_dir), SOURCES))
     tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -251,6 +251,17 @@ int residual_into(px_ctx *ctx, int dtype, const void *phi, int n, int ld, const 
 
 }  // namespace
 
+int px::set_error(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
 extern "C" {
 
 const char *px_last_error(void) { return g_err.c_str(); }
@@ -713,6 +724,174 @@ int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *o,
             S.seconds = secs;
         }
     return st ? fail(st, "%s", err) : PX_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- learned correction
+
+extern "C" {
+
+int px_net_make_pair(const double *phi, int n, int ld, int loss, float *x, float *t, px_ctx *ctx, void *stream)
+{
+    int st = check_n_ld(n, ld, F64);
+    if (st) return st;
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = check_ptr(phi, F64, "phi"))) return st;
+    if (!x || !t) return fail(PX_EINVAL, "x or t is NULL");
+    if (loss != PX_LOSS_MSE && loss != PX_LOSS_ENERGY) return fail(PX_EINVAL, "unknown loss %d", loss);
+    const size_t gb = grid_bytes(n, ld, F64), xb = sizeof(float) * (size_t)n * n;
+    if (overlap(x, xb, phi, gb) || overlap(t, xb, phi, gb) || overlap(x, xb, t, xb))
+        return fail(PX_EALIAS, "x, t and phi must not overlap");
+    if ((st = set_device(ctx))) return st;
+    const size_t pb = sizeof(double) * 2 * (size_t)pair_num_blocks(n);
+    if ((st = ensure_mix(ctx, pb + 2 * sizeof(double)))) return st;
+    double *part = static_cast<double *>(ctx->mix);
+    PX_HIP(pair_launch(phi, n, ld, loss, x, t, part, part + pb / sizeof(double), (hipStream_t)stream),
+           "pair kernel launch");
+    return PX_OK;
+}
+
+int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double h, double lambda, px_net *net,
+                     const px_learned_opts *o, px_learned_stats *stats, px_ctx *ctx, void *stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    int st = check_n_ld(n, ld, F64);
+    if (st) return st;
+    if (!o) return fail(PX_EINVAL, "opts is NULL");
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = check_ptr(phi, F64, "phi"))) return st;
+    if ((st = check_flat(f, n, ld_f, F64, "f"))) return st;
+    if ((st = check_pos(h, "h")) || (st = check_pos(lambda, "lambda"))) return st;
+    if (!(o->rtol >= 0.0) || !std::isfinite(o->rtol)) return fail(PX_EINVAL, "rtol must be finite and >= 0");
+    if (o->norm != 0 && o->norm != 1) return fail(PX_EINVAL, "norm must be 0 (max) or 1 (L2)");
+    if (o->max_sweeps < 0) return fail(PX_EINVAL, "max_sweeps < 0");
+    if (o->smooth_sweeps < 1) return fail(PX_EINVAL, "smooth_sweeps must be >= 1");
+    if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
+    if (o->use_net != 0 && o->use_net != 1) return fail(PX_EINVAL, "use_net must be 0 or 1");
+    if (o->use_net && !net) return fail(PX_EINVAL, "use_net needs a network");
+    if (o->use_net && net_device(net) != ctx->device)
+        return fail(PX_EINVAL, "network on device %d, context on device %d", net_device(net), ctx->device);
+    const size_t gb = grid_bytes(n, ld, F64);
+    if (overlap(f, flat_bytes(n, ld_f, F64), phi, gb)) return fail(PX_EALIAS, "phi overlaps f");
+    if ((st = set_device(ctx))) return st;
+    if ((st = ensure_norms(ctx))) return st;
+    if ((st = ensure_grid(ctx, gb))) return st;
+    // scratch: saved iterate | r (FP64) | network output (FP32) | double2 partials | dots
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const int ld_r = (n + 31) / 32 * 32, ld_y = (n + 63) / 64 * 64;
+    const size_t o_r = up(gb), o_y = o_r + up(sizeof(double) * (size_t)n * ld_r);
+    const size_t o_p = o_y + up(sizeof(float) * (size_t)n * ld_y);
+    const size_t o_d = o_p + up(sizeof(double) * 2 * (size_t)pair_num_blocks(n));
+    if ((st = ensure_mix(ctx, o_d + 256))) return st;
+    char *mb = static_cast<char *>(ctx->mix);
+    double *save = reinterpret_cast<double *>(mb);
+    double *r = reinterpret_cast<double *>(mb + o_r);
+    float *y = reinterpret_cast<float *>(mb + o_y);
+    double *part = reinterpret_cast<double *>(mb + o_p);
+    double *dots = reinterpret_cast<double *>(mb + o_d);
+    hipStream_t s = (hipStream_t)stream;
+    const int k = o->tblock ? o->tblock : default_tblock(ctx, F64, n, ld);
+    const double c = 1.0 / (h * h);
+
+    auto read_norms = [&](double *dst) -> int {
+        PX_HIP(hipMemcpyAsync(ctx->norms_host, ctx->norms_dev, 2 * sizeof(double), hipMemcpyDeviceToHost, s),
+               "norm readback");
+        PX_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+        dst[0] = ctx->norms_host[0];
+        dst[1] = ctx->norms_host[1];
+        return PX_OK;
+    };
+    auto measure = [&](const double *nr) { return o->norm == 0 ? nr[0] : std::sqrt(nr[1]); };
+
+    double fn[2];
+    PX_HIP(zero_grid_launch(F64, ctx->grid, n, ld, s), "zero kernel launch");
+    if ((st = residual_into(ctx, F64, ctx->grid, n, ld, f, ld_f, h, GHOST_FIXED, nullptr, 0, ctx->norms_dev, s)))
+        return st;
+    if ((st = read_norms(fn))) return st;
+    const double fref = measure(fn);
+    const double target = o->rtol * fref;
+
+    px_learned_stats S;
+    std::memset(&S, 0, sizeof S);
+    double nr[2] = {0, 0};
+    int result = PX_OK;
+    void *cur = phi;
+    void *oth = ctx->grid;
+    bool correct = true;
+
+    // sweeps cur -> ... in single-launch chunks of k (cur ends on the last output)
+    auto smooth = [&](int todo, bool norms_at_end) -> int {
+        int done = 0;
+        while (done < todo) {
+            const int ks = std::min(k, todo - done);
+            const bool last = done + ks == todo;
+            int e = run_sweeps(ctx, F64, cur, oth, nullptr, n, ld, f, ld_f, h, lambda, ks, ks, DIRICHLET0,
+                               (last && norms_at_end) ? RES_FINAL : RES_NONE, ctx->norms_dev, s);
+            if (e) return e;
+            std::swap(cur, oth);
+            done += ks;
+        }
+        return PX_OK;
+    };
+
+    if ((st = residual_into(ctx, F64, cur, n, ld, f, ld_f, h, DIRICHLET0, r, ld_r, ctx->norms_dev, s))) return st;
+    if ((st = read_norms(nr))) return st;
+    const double r0 = measure(nr);
+    for (;;) {
+        const double m = measure(nr);
+        if (!std::isfinite(nr[0]) || !std::isfinite(nr[1])) { result = fail(PX_ENONFINITE, "non-finite residual"); break; }
+        if (m <= target) break;
+        if (m > 1e8 * std::max(r0, fref)) { result = fail(PX_EDIVERGED, "residual grew from %g to %g", r0, m); break; }
+        if (S.base.sweeps >= o->max_sweeps) { result = fail(PX_ENOTCONV, "max_sweeps reached (rel res %g)", m / fref); break; }
+        const int todo = (int)std::min<int64_t>(o->smooth_sweeps, o->max_sweeps - S.base.sweeps);
+        if (correct) {
+            PX_HIP(copy_grid_launch(F64, cur, save, n, ld, s), "copy kernel launch");
+            const double rms = std::sqrt(nr[1] / ((double)n * (double)n));
+            const void *d = r;
+            int ddt = F64, ld_d = ld_r;
+            if (o->use_net) {
+                PX_HIP(net_infer(net, r, ld_r, n, 1.0 / rms, y, ld_y, s), "network forward launch");
+                d = y;
+                ddt = F32;
+                ld_d = ld_y;
+            }
+            PX_HIP(dots_launch(ddt, d, ld_d, r, ld_r, n, part, dots, s), "dots kernel launch");
+            PX_HIP(step_launch(ddt, d, ld_d, static_cast<double *>(cur), n, ld, c, dots, s), "step kernel launch");
+            if ((st = smooth(todo, false))) return st;
+            if ((st = residual_into(ctx, F64, cur, n, ld, f, ld_f, h, DIRICHLET0, r, ld_r, ctx->norms_dev, s)))
+                return st;
+            double nn[2];
+            if ((st = read_norms(nn))) return st;
+            if (std::isfinite(nn[0]) && std::isfinite(nn[1]) && nn[1] < nr[1]) {
+                S.corrections += 1;
+                S.base.sweeps += todo;
+                S.base.outer_steps += 1;
+                nr[0] = nn[0];
+                nr[1] = nn[1];
+            } else {
+                // the judge: undo the step and continue with plain relaxation only
+                PX_HIP(copy_grid_launch(F64, save, cur, n, ld, s), "copy kernel launch");
+                S.rejected += 1;
+                S.fell_back = 1;
+                correct = false;
+            }
+        } else {
+            if ((st = smooth(todo, true))) return st;
+            S.base.sweeps += todo;
+            S.base.outer_steps += 1;
+            if ((st = read_norms(nr))) return st;
+        }
+    }
+    if (cur != phi) PX_HIP(copy_grid_launch(F64, cur, phi, n, ld, s), "copy kernel launch");
+    PX_HIP(hipStreamSynchronize(s), "hipStreamSynchronize");
+    S.base.res_max = nr[0];
+    S.base.res_l2 = std::sqrt(nr[1]);
+    S.base.rel_res_max = fn[0] > 0 ? nr[0] / fn[0] : nr[0];
+    S.base.rel_res_l2 = fn[1] > 0 ? std::sqrt(nr[1] / fn[1]) : S.base.res_l2;
+    S.base.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = S;
+    return result;
 }
 
 }  // extern "C"

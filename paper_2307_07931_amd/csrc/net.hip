@@ -1,0 +1,829 @@
+// net.hip -- the learned correction network: forward, backward and Adam on gfx950.
+//
+// Network (not from the paper; an extension): x -> conv3x3 1->32 -> ReLU ->
+// conv3x3 32->32 -> ReLU -> conv3x3 32->32 -> ReLU -> conv3x3 32->1 -> y, no bias,
+// zero padding.  BF16 weights and activations, FP32 accumulation.
+//
+// * The two 32->32 layers (96% of the arithmetic) run as implicit GEMMs on the
+//   matrix cores: one wavefront computes 32 output channels x 32 pixels of one
+//   image row with v_mfma_f32_32x32x16_bf16, K = 9 taps x 32 channels = 18
+//   instructions.  The same kernel computes the input gradient (transposed
+//   convolution: taps mirrored, weights in [tap][in][out] order) with the ReLU
+//   mask of the layer's input applied in the epilogue.
+// * Layer 1 (1 input channel) and layer 4 (1 output channel) are thin; they run on
+//   the vector ALUs.
+// * Weight gradients are reductions over all pixels: every block sums a fixed
+//   pixel range into private partials, and a second kernel adds the partials in
+//   block order, so results are deterministic.
+// Activations are stored channels-last (pixel-major, 32 channels = 64 bytes).
+#include "../../include/protox.h"
+#include "px_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace px {
+namespace {
+
+constexpr int C = 32;          // hidden channels
+constexpr int NW1 = C * 9;     // layer 1 weights
+constexpr int NW2 = C * C * 9; // layer 2 / 3 weights
+constexpr int NW4 = C * 9;     // layer 4 weights
+constexpr int NPARAM = NW1 + 2 * NW2 + NW4;  // 19008
+constexpr int OFF2 = NW1, OFF3 = NW1 + NW2, OFF4 = NW1 + 2 * NW2;
+constexpr int WG_BLOCKS = 512; // split-K blocks of the weight gradients
+constexpr int BX = 256;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float bfv(bf16 x) { return bf16_to_f32(x.bits); }
+__device__ __forceinline__ bf16 tobf(float x) { return bf16{f32_to_bf16_rne(x)}; }
+
+// tap t = 3a + c reads offset (a - 1, c - 1); the transposed convolution reads (1 - a, 1 - c)
+__device__ __forceinline__ int tap_dy(int t, bool mirror) { return mirror ? 1 - t / 3 : t / 3 - 1; }
+__device__ __forceinline__ int tap_dx(int t, bool mirror) { return mirror ? 1 - t % 3 : t % 3 - 1; }
+
+struct NetW {
+    bf16 *w1;   // [co][t]
+    bf16 *w2f;  // [t][co][ci]  (forward: rows = output channel, k = input channel)
+    bf16 *w2b;  // [t][ci][co]  (input gradient: rows = input channel, k = output channel)
+    bf16 *w3f, *w3b;
+    bf16 *w4;   // [ci][t]
+};
+
+__global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restrict__ w, NetW nw)
+{
+    const int q = blockIdx.x * BX + threadIdx.x;
+    if (q >= NPARAM) return;
+    const bf16 b = tobf(w[q]);
+    if (q < OFF2) {
+        nw.w1[q] = b;  // (co, 1, a, c) -> co*9 + t
+    } else if (q < OFF4) {
+        const bool l3 = q >= OFF3;
+        const int r = q - (l3 ? OFF3 : OFF2);
+        const int co = r / (C * 9), ci = (r / 9) % C, t = r % 9;
+        (l3 ? nw.w3f : nw.w2f)[(t * C + co) * C + ci] = b;
+        (l3 ? nw.w3b : nw.w2b)[(t * C + ci) * C + co] = b;
+    } else {
+        nw.w4[q - OFF4] = b;  // (1, ci, a, c) -> ci*9 + t
+    }
+}
+
+// Layer 1: x (rows of ldx, FP64 or FP32) times `scale`, rounded to FP32 and then to
+// BF16, -> 32 channels, ReLU.
+template <typename TX>
+__global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, int ldx, double scale,
+                                                    const bf16 *__restrict__ w1, bf16 *__restrict__ a1, int B,
+                                                    int H, int W)
+{
+    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
+    if (p >= (long long)B * H * W) return;
+    const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+    float xv[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
+        const bool ok = ii >= 0 && ii < H && jj >= 0 && jj < W;
+        const float v = ok ? (float)((double)x[((long long)b * H + ii) * ldx + jj] * scale) : 0.0f;
+        xv[t] = bf16_to_f32(f32_to_bf16_rne(v));
+    }
+    bf16 out[C];
+#pragma unroll
+    for (int co = 0; co < C; ++co) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += bfv(w1[co * 9 + t]) * xv[t];
+        out[co] = tobf(fmaxf(acc, 0.0f));
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(a1 + p * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(out)[q];
+}
+
+// 32 -> 32 convolution on the matrix cores.  One wave: 32 output channels x 32 pixels
+// (j0 .. j0+31 of row i of image b).  A = weights (rows: output channel, k: input
+// channel within a tap), B = input patches (k: input channel, columns: pixels).
+// MIRROR computes the input gradient: in = gradient of the layer output, weights in
+// [t][ci][co] order, taps mirrored, and the result is multiplied by the ReLU mask of
+// `mask` (the layer's input activation).  Otherwise the epilogue applies ReLU.
+template <bool MIRROR>
+__global__ __launch_bounds__(BX) void conv32_mfma_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wl,
+                                                         bf16 *__restrict__ out, const bf16 *__restrict__ mask,
+                                                         int B, int H, int W)
+{
+    const int lane = threadIdx.x & 63;
+    const int tiles_w = (W + 31) / 32;
+    const long long wave = (long long)blockIdx.x * (BX / 64) + (threadIdx.x >> 6);
+    if (wave >= (long long)B * H * tiles_w) return;
+    const int tj = (int)(wave % tiles_w), i = (int)((wave / tiles_w) % H), b = (int)(wave / ((long long)tiles_w * H));
+    const int n = lane & 31, kg = lane >> 5;
+    const int j = tj * 32 + n;
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ii = i + tap_dy(t, MIRROR), jj = j + tap_dx(t, MIRROR);
+        const bool ok = ii >= 0 && ii < H && jj >= 0 && jj < W;
+        const long long src = ok ? (((long long)b * H + ii) * W + jj) * C : 0;
+#pragma unroll
+        for (int c16 = 0; c16 < 2; ++c16) {
+            const int k0 = c16 * 16 + kg * 8;
+            uint4 bu = *reinterpret_cast<const uint4 *>(in + src + k0);
+            if (!ok) bu = make_uint4(0, 0, 0, 0);
+            const uint4 au = *reinterpret_cast<const uint4 *>(wl + (t * C + n) * C + k0);
+            bf16x8 av, bv;
+            __builtin_memcpy(&av, &au, 16);
+            __builtin_memcpy(&bv, &bu, 16);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    if (j >= W) return;
+    const long long p = ((long long)b * H + i) * W + j;
+    // lane holds output channels 8g + 4*kg + e (e = 0..3) of pixel j, in acc[4g + e]
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const int co = 8 * g + 4 * kg;
+        unsigned short v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float a = acc[4 * g + e];
+            if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
+            else a = fmaxf(a, 0.0f);
+            v[e] = f32_to_bf16_rne(a);
+        }
+        uint2 pk;
+        pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
+        pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
+        *reinterpret_cast<uint2 *>(out + p * C + co) = pk;
+    }
+}
+
+// Layer 4: 32 channels -> 1, output FP32 into rows of ldy.
+__global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const bf16 *__restrict__ w4,
+                                                    float *__restrict__ y, int ldy, int B, int H, int W)
+{
+    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
+    if (p >= (long long)B * H * W) return;
+    const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+    float acc = 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
+        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+        const bf16 *a = a3 + (((long long)b * H + ii) * W + jj) * C;
+#pragma unroll
+        for (int ci = 0; ci < C; ++ci) acc += bfv(w4[ci * 9 + t]) * bfv(a[ci]);
+    }
+    y[((long long)b * H + i) * ldy + j] = acc;
+}
+
+// Fixed-order block reduction of one double per thread; thread 0 gets the total.
+__device__ __forceinline__ double block_sum(double v, double *sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int h = BX / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + h];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// Mean squared error: dy = 2 (y - t) / N, per-block partial sums of (y - t)^2.
+__global__ __launch_bounds__(BX) void mse_kernel(const float *__restrict__ y, const float *__restrict__ tg,
+                                                 float *__restrict__ dy, double *__restrict__ part, long long N)
+{
+    __shared__ double sh[BX];
+    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
+    double e2 = 0.0;
+    if (p < N) {
+        const float d = y[p] - tg[p];
+        dy[p] = (float)(2.0 / (double)N) * d;
+        e2 = (double)d * (double)d;
+    }
+    const double tot = block_sum(e2, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+// Energy loss, first pass: y <- y - t.
+__global__ __launch_bounds__(BX) void diff_kernel(float *__restrict__ y, const float *__restrict__ tg, long long N)
+{
+    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
+    if (p < N) y[p] = y[p] - tg[p];
+}
+
+// Energy loss, second pass on d = y - t: kd = 4 d - (sum of the 4 neighbours), a
+// neighbour outside the image being -d (odd reflection); dy = 2 kd / N, partial sums of
+// d * kd.
+__global__ __launch_bounds__(BX) void energy_kernel(const float *__restrict__ d, float *__restrict__ dy,
+                                                    double *__restrict__ part, int B, int H, int W)
+{
+    __shared__ double sh[BX];
+    const long long N = (long long)B * H * W;
+    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
+    double e = 0.0;
+    if (p < N) {
+        const int j = (int)(p % W), i = (int)((p / W) % H);
+        const float c = d[p];
+        const float dn = i > 0 ? d[p - W] : -c;
+        const float ds = i < H - 1 ? d[p + W] : -c;
+        const float dw = j > 0 ? d[p - 1] : -c;
+        const float de = j < W - 1 ? d[p + 1] : -c;
+        const float kd = 4.0f * c - (((dn + dw) + de) + ds);
+        dy[p] = (float)(2.0 / (double)N) * kd;
+        e = (double)c * (double)kd;
+    }
+    const double tot = block_sum(e, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(BX) void sum_partials_kernel(const double *__restrict__ part, int count,
+                                                          double *__restrict__ out, double mul)
+{
+    __shared__ double sh[BX];
+    double s = 0.0;
+    for (int k = threadIdx.x; k < count; k += BX) s = s + part[k];
+    const double tot = block_sum(s, sh);
+    if (threadIdx.x == 0) *out = tot * mul;
+}
+
+// Two fixed-order sums of double2 partials: out[0] = sum .x, out[1] = sum .y.
+__global__ __launch_bounds__(BX) void sum2_partials_kernel(const double2 *__restrict__ part, int count,
+                                                           double *__restrict__ out)
+{
+    __shared__ double sh[BX];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < count; k += BX) {
+        a = a + part[k].x;
+        b = b + part[k].y;
+    }
+    const double ta = block_sum(a, sh);
+    __syncthreads();
+    const double tb = block_sum(b, sh);
+    if (threadIdx.x == 0) {
+        out[0] = ta;
+        out[1] = tb;
+    }
+}
+
+// Layer-4 input gradient: dz3[p][ci] = (sum_t dy[p - off_t] w4[ci][t]) * (a3[p][ci] > 0).
+__global__ __launch_bounds__(BX) void l4_bwd_kernel(const float *__restrict__ dy, const bf16 *__restrict__ w4,
+                                                    const bf16 *__restrict__ a3, bf16 *__restrict__ dz3, int B,
+                                                    int H, int W)
+{
+    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
+    if (p >= (long long)B * H * W) return;
+    const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+    float d[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ii = i + tap_dy(t, true), jj = j + tap_dx(t, true);
+        d[t] = (ii >= 0 && ii < H && jj >= 0 && jj < W) ? dy[((long long)b * H + ii) * W + jj] : 0.0f;
+    }
+    bf16 out[C];
+#pragma unroll
+    for (int ci = 0; ci < C; ++ci) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += d[t] * bfv(w4[ci * 9 + t]);
+        out[ci] = tobf(bfv(a3[p * C + ci]) > 0.0f ? acc : 0.0f);
+    }
+    uint4 *dst = reinterpret_cast<uint4 *>(dz3 + p * C);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(out)[q];
+}
+
+// Weight gradient of a 32->32 layer, split over WG_BLOCKS pixel ranges:
+// part[blk][(co*32 + ci)*9 + t] = sum_{p in range} dz[p][co] * act[p + off_t][ci].
+// Thread (ci = tid % 32, co = 4*(tid/32) .. +3) keeps 36 sums.
+__global__ __launch_bounds__(BX) void wgrad32_kernel(const bf16 *__restrict__ act, const bf16 *__restrict__ dz,
+                                                     float *__restrict__ part, int B, int H, int W)
+{
+    const long long N = (long long)B * H * W;
+    const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
+    const int ci = threadIdx.x & 31, cq = (threadIdx.x >> 5) * 4;
+    float acc[4][9];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[q][t] = 0.0f;
+    for (long long p = p0; p < p1; ++p) {
+        const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+        float g[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) g[q] = bfv(dz[p * C + cq + q]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
+            const float a = (ii >= 0 && ii < H && jj >= 0 && jj < W)
+                                ? bfv(act[(((long long)b * H + ii) * W + jj) * C + ci]) : 0.0f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q][t] += g[q] * a;
+        }
+    }
+    float *dst = part + (size_t)blockIdx.x * NW2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) dst[((cq + q) * C + ci) * 9 + t] = acc[q][t];
+}
+
+// Weight gradient of layer 1: part[blk][co*9 + t] = sum dz1[p][co] * a0[p + off_t]
+// (a0 = BF16 of x * scale, as the forward pass used).
+__global__ __launch_bounds__(NW1) void wgrad1_kernel(const float *__restrict__ x, int ldx, const bf16 *__restrict__ dz1,
+                                                     float *__restrict__ part, int B, int H, int W)
+{
+    const long long N = (long long)B * H * W;
+    const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
+    const int co = threadIdx.x / 9, t = threadIdx.x % 9;
+    float acc = 0.0f;
+    for (long long p = p0; p < p1; ++p) {
+        const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
+        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+        const float a0 = bf16_to_f32(f32_to_bf16_rne(x[((long long)b * H + ii) * ldx + jj]));
+        acc += bfv(dz1[p * C + co]) * a0;
+    }
+    part[(size_t)blockIdx.x * NW1 + threadIdx.x] = acc;
+}
+
+// Weight gradient of layer 4: part[blk][ci*9 + t] = sum dy[p] * a3[p + off_t][ci].
+__global__ __launch_bounds__(NW4) void wgrad4_kernel(const bf16 *__restrict__ a3, const float *__restrict__ dy,
+                                                     float *__restrict__ part, int B, int H, int W)
+{
+    const long long N = (long long)B * H * W;
+    const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
+    const int ci = threadIdx.x / 9, t = threadIdx.x % 9;
+    float acc = 0.0f;
+    for (long long p = p0; p < p1; ++p) {
+        const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
+        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
+        acc += dy[p] * bfv(a3[(((long long)b * H + ii) * W + jj) * C + ci]);
+    }
+    part[(size_t)blockIdx.x * NW4 + threadIdx.x] = acc;
+}
+
+// g[off + q] = sum over blocks (in block order) of part[blk][q].
+__global__ __launch_bounds__(BX) void reduce_wgrad_kernel(const float *__restrict__ part, int nblk, int count,
+                                                          float *__restrict__ g)
+{
+    const int q = blockIdx.x * BX + threadIdx.x;
+    if (q >= count) return;
+    float s = 0.0f;
+    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * count + q];
+    g[q] = s;
+}
+
+__global__ __launch_bounds__(BX) void adam_kernel(float *__restrict__ w, const float *__restrict__ g,
+                                                  float *__restrict__ m, float *__restrict__ v, float lr,
+                                                  float b1, float b2, float eps, float c1, float c2)
+{
+    const int q = blockIdx.x * BX + threadIdx.x;
+    if (q >= NPARAM) return;
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.0f - b1) * gq;
+    const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    w[q] -= lr * (mq / c1) / (sqrtf(vq / c2) + eps);
+}
+
+// ---- pieces of the learned refinement (FP64 grids, odd reflection at the edges)
+
+// 5-point stencil of an n x n field v (rows of ldv) at (i, j), reading only the n x n
+// interior: a neighbour outside is -v(i, j).  Sum order ((((N - 4C) + W) + E) + S).
+template <typename TV>
+__device__ __forceinline__ double stencil_odd(const TV *__restrict__ v, int ldv, int n, int i, int j)
+{
+    const double c = (double)v[(long long)i * ldv + j];
+    const double vn = i > 0 ? (double)v[(long long)(i - 1) * ldv + j] : -c;
+    const double vs = i < n - 1 ? (double)v[(long long)(i + 1) * ldv + j] : -c;
+    const double vw = j > 0 ? (double)v[(long long)i * ldv + j - 1] : -c;
+    const double ve = j < n - 1 ? (double)v[(long long)i * ldv + j + 1] : -c;
+    return (((vn - 4.0 * c) + vw) + ve) + vs;
+}
+
+// Pair, first pass over phi's interior (phi + ld + 1 is cell (1, 1)): per-block partial
+// sums {S(phi)^2, e^2 or e K e} with e = -phi and K e = -S(e) = S(phi).
+__global__ __launch_bounds__(BX) void pair_sums_kernel(const double *__restrict__ phi, int n, int ld, int loss,
+                                                       double2 *__restrict__ part)
+{
+    __shared__ double sh[BX];
+    const int i = blockIdx.y, j = blockIdx.x * BX + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (j < n) {
+        const double *in = phi + ld + 1;
+        const double sp = stencil_odd(in, ld, n, i, j);
+        const double e = -in[(long long)i * ld + j];
+        a = sp * sp;
+        b = loss == 1 ? e * sp : e * e;
+    }
+    const double ta = block_sum(a, sh);
+    __syncthreads();
+    const double tb = block_sum(b, sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(ta, tb);
+}
+
+// Pair, second pass: x = -S(phi) / sqrt(sums[0] / n^2), t = -phi / sqrt(sums[1] / n^2).
+__global__ __launch_bounds__(BX) void pair_write_kernel(const double *__restrict__ phi, int n, int ld,
+                                                        const double *__restrict__ sums, float *__restrict__ x,
+                                                        float *__restrict__ t)
+{
+    const int i = blockIdx.y, j = blockIdx.x * BX + threadIdx.x;
+    if (j >= n) return;
+    const double cells = (double)n * (double)n;
+    const double rx = sqrt(sums[0] / cells), rt = sqrt(sums[1] / cells);
+    const double *in = phi + ld + 1;
+    const double sp = stencil_odd(in, ld, n, i, j);
+    x[(long long)i * n + j] = rx > 0.0 ? (float)(-sp / rx) : 0.0f;
+    t[(long long)i * n + j] = rt > 0.0 ? (float)(-in[(long long)i * ld + j] / rt) : 0.0f;
+}
+
+// Per-block partial sums {<r, d>, <d, S d>} over the n x n interior.
+template <typename TD>
+__global__ __launch_bounds__(BX) void dots_kernel(const TD *__restrict__ d, int ld_d, const double *__restrict__ r,
+                                                  int ld_r, int n, double2 *__restrict__ part)
+{
+    __shared__ double sh[BX];
+    const int i = blockIdx.y, j = blockIdx.x * BX + threadIdx.x;
+    double a = 0.0, b = 0.0;
+    if (j < n) {
+        const double dv = (double)d[(long long)i * ld_d + j];
+        a = r[(long long)i * ld_r + j] * dv;
+        b = dv * stencil_odd(d, ld_d, n, i, j);
+    }
+    const double ta = block_sum(a, sh);
+    __syncthreads();
+    const double tb = block_sum(b, sh);
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(ta, tb);
+}
+
+// phi(i, j) += a d(i, j) over the interior, a = dots[0] / (c dots[1]), 0 if dots[1] == 0.
+template <typename TD>
+__global__ __launch_bounds__(BX) void step_kernel(const TD *__restrict__ d, int ld_d, double *__restrict__ phi, int n,
+                                                  int ld, double c, const double *__restrict__ dots)
+{
+    const int i = blockIdx.y, j = blockIdx.x * BX + threadIdx.x;
+    if (j >= n) return;
+    const double den = c * dots[1];
+    const double a = den != 0.0 ? dots[0] / den : 0.0;
+    double *p = phi + (long long)(i + 1) * ld + (j + 1);
+    *p = *p + a * (double)d[(long long)i * ld_d + j];
+}
+
+inline unsigned blocks_for(long long n) { return (unsigned)((n + BX - 1) / BX); }
+
+// ---- network state
+
+struct NetState {
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    bf16 *wb = nullptr;  // all BF16 layouts in one allocation
+    NetW nw{};
+    long long pixels = 0;  // workspace capacity
+    bf16 *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *dz1 = nullptr, *dz2 = nullptr, *dz3 = nullptr;
+    float *y = nullptr, *dy = nullptr, *part = nullptr;
+    double *dpart = nullptr;
+    long long step = 0;
+    long long last_pixels = 0;  // pixels of the last forward pass (0: none yet)
+
+    void free_workspace()
+    {
+        for (bf16 **p : {&a1, &a2, &a3, &dz1, &dz2, &dz3}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        for (float **p : {&y, &dy}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        if (dpart) (void)hipFree(dpart);
+        dpart = nullptr;
+        pixels = 0;
+    }
+    ~NetState()
+    {
+        free_workspace();
+        for (float **p : {&w, &m, &v, &g, &part}) {
+            if (*p) (void)hipFree(*p);
+            *p = nullptr;
+        }
+        if (wb) (void)hipFree(wb);
+    }
+};
+
+hipError_t net_alloc(NetState &s)
+{
+    hipError_t e;
+    for (float **p : {&s.w, &s.m, &s.v, &s.g})
+        if ((e = hipMalloc(p, sizeof(float) * NPARAM)) != hipSuccess) return e;
+    if ((e = hipMalloc(&s.wb, sizeof(bf16) * (NW1 + 4 * NW2 + NW4))) != hipSuccess) return e;
+    s.nw.w1 = s.wb;
+    s.nw.w2f = s.wb + NW1;
+    s.nw.w2b = s.nw.w2f + NW2;
+    s.nw.w3f = s.nw.w2b + NW2;
+    s.nw.w3b = s.nw.w3f + NW2;
+    s.nw.w4 = s.nw.w3b + NW2;
+    return hipMalloc(&s.part, sizeof(float) * (size_t)WG_BLOCKS * NW2);
+}
+
+hipError_t net_set(NetState &s, const float *host)
+{
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+    if ((e = hipMemcpy(s.w, host, sizeof(float) * NPARAM, hipMemcpyHostToDevice)) != hipSuccess) return e;
+    if ((e = hipMemset(s.m, 0, sizeof(float) * NPARAM)) != hipSuccess) return e;
+    if ((e = hipMemset(s.v, 0, sizeof(float) * NPARAM)) != hipSuccess) return e;
+    if ((e = hipMemset(s.g, 0, sizeof(float) * NPARAM)) != hipSuccess) return e;
+    s.step = 0;
+    hipLaunchKernelGGL(prep_weights_kernel, dim3(blocks_for(NPARAM)), dim3(BX), 0, 0, s.w, s.nw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipDeviceSynchronize();
+}
+
+hipError_t net_workspace(NetState &s, long long pixels)
+{
+    if (pixels <= s.pixels) return hipSuccess;
+    hipError_t e;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return e;
+    s.free_workspace();
+    for (bf16 **p : {&s.a1, &s.a2, &s.a3, &s.dz1, &s.dz2, &s.dz3})
+        if ((e = hipMalloc(p, sizeof(bf16) * C * (size_t)pixels)) != hipSuccess) return e;
+    for (float **p : {&s.y, &s.dy})
+        if ((e = hipMalloc(p, sizeof(float) * (size_t)pixels)) != hipSuccess) return e;
+    if ((e = hipMalloc(&s.dpart, sizeof(double) * blocks_for(pixels))) != hipSuccess) return e;
+    s.pixels = pixels;
+    return hipSuccess;
+}
+
+unsigned conv_blocks(int B, int H, int W)
+{
+    return (unsigned)(((long long)B * H * ((W + 31) / 32) + (BX / 64) - 1) / (BX / 64));
+}
+
+// Forward pass: y (rows of ldy) = N(x * scale); x rows of ldx, FP64 or FP32.
+hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scale, float *y, int ldy, int B, int H,
+                       int W, hipStream_t st)
+{
+    const long long N = (long long)B * H * W;
+    hipError_t e = net_workspace(s, N);
+    if (e != hipSuccess) return e;
+    if (xdt == F64)
+        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(blocks_for(N)), dim3(BX), 0, st, (const double *)x, ldx,
+                           scale, s.nw.w1, s.a1, B, H, W);
+    else
+        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(blocks_for(N)), dim3(BX), 0, st, (const float *)x, ldx, scale,
+                           s.nw.w1, s.a1, B, H, W);
+    hipLaunchKernelGGL(conv32_mfma_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a1, s.nw.w2f, s.a2,
+                       (const bf16 *)nullptr, B, H, W);
+    hipLaunchKernelGGL(conv32_mfma_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
+                       (const bf16 *)nullptr, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
+    s.last_pixels = N;
+    return hipGetLastError();
+}
+
+// Forward, loss and backward on compact FP32 x and t; gradient into s.g, loss into *loss.
+hipError_t net_gradient(NetState &s, const float *x, const float *t, int B, int H, int W, int loss,
+                        double *loss_out, hipStream_t st)
+{
+    const long long N = (long long)B * H * W;
+    hipError_t e = net_workspace(s, N);
+    if (e != hipSuccess) return e;
+    if ((e = net_forward(s, F32, x, W, 1.0, s.y, W, B, H, W, st)) != hipSuccess) return e;
+    if (loss == 0) {
+        hipLaunchKernelGGL(mse_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.y, t, s.dy, s.dpart, N);
+    } else {
+        hipLaunchKernelGGL(diff_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.y, t, N);
+        hipLaunchKernelGGL(energy_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.y, s.dy, s.dpart, B, H, W);
+    }
+    if (loss_out)
+        hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(BX), 0, st, s.dpart, (int)blocks_for(N), loss_out,
+                           1.0 / (double)N);
+    const unsigned cb = conv_blocks(B, H, W);
+    // layer 4
+    hipLaunchKernelGGL(wgrad4_kernel, dim3(WG_BLOCKS), dim3(NW4), 0, st, s.a3, s.dy, s.part, B, H, W);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW4)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW4,
+                       s.g + OFF4);
+    hipLaunchKernelGGL(l4_bwd_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.dy, s.nw.w4, s.a3, s.dz3, B, H, W);
+    // layer 3
+    hipLaunchKernelGGL(wgrad32_kernel, dim3(WG_BLOCKS), dim3(BX), 0, st, s.a2, s.dz3, s.part, B, H, W);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW2,
+                       s.g + OFF3);
+    hipLaunchKernelGGL(conv32_mfma_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz3, s.nw.w3b, s.dz2, s.a2, B, H, W);
+    // layer 2
+    hipLaunchKernelGGL(wgrad32_kernel, dim3(WG_BLOCKS), dim3(BX), 0, st, s.a1, s.dz2, s.part, B, H, W);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW2,
+                       s.g + OFF2);
+    hipLaunchKernelGGL(conv32_mfma_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz2, s.nw.w2b, s.dz1, s.a1, B, H, W);
+    // layer 1
+    hipLaunchKernelGGL(wgrad1_kernel, dim3(WG_BLOCKS), dim3(NW1), 0, st, x, W, s.dz1, s.part, B, H, W);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW1)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW1, s.g);
+    return hipGetLastError();
+}
+
+hipError_t net_adam(NetState &s, float lr, hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    s.step += 1;
+    const float c1 = 1.0f - std::pow(b1, (float)s.step), c2 = 1.0f - std::pow(b2, (float)s.step);
+    hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(NPARAM)), dim3(BX), 0, st, s.w, s.g, s.m, s.v, lr, b1, b2, eps,
+                       c1, c2);
+    hipLaunchKernelGGL(prep_weights_kernel, dim3(blocks_for(NPARAM)), dim3(BX), 0, st, s.w, s.nw);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int pair_num_blocks(int n) { return (int)blocks_for(n) * n; }
+
+hipError_t pair_launch(const double *phi, int n, int ld, int loss, float *x, float *t, double *part, double *sums,
+                       hipStream_t s)
+{
+    const dim3 grid(blocks_for(n), n);
+    hipLaunchKernelGGL(pair_sums_kernel, grid, dim3(BX), 0, s, phi, n, ld, loss, (double2 *)part);
+    hipLaunchKernelGGL(sum2_partials_kernel, dim3(1), dim3(BX), 0, s, (const double2 *)part, pair_num_blocks(n),
+                       sums);
+    hipLaunchKernelGGL(pair_write_kernel, grid, dim3(BX), 0, s, phi, n, ld, (const double *)sums, x, t);
+    return hipGetLastError();
+}
+
+hipError_t dots_launch(int ddtype, const void *d, int ld_d, const double *r, int ld_r, int n, double *part,
+                       double *dots, hipStream_t s)
+{
+    const dim3 grid(blocks_for(n), n);
+    if (ddtype == F64)
+        hipLaunchKernelGGL(dots_kernel<double>, grid, dim3(BX), 0, s, (const double *)d, ld_d, r, ld_r, n,
+                           (double2 *)part);
+    else
+        hipLaunchKernelGGL(dots_kernel<float>, grid, dim3(BX), 0, s, (const float *)d, ld_d, r, ld_r, n,
+                           (double2 *)part);
+    hipLaunchKernelGGL(sum2_partials_kernel, dim3(1), dim3(BX), 0, s, (const double2 *)part, pair_num_blocks(n),
+                       dots);
+    return hipGetLastError();
+}
+
+hipError_t step_launch(int ddtype, const void *d, int ld_d, double *phi, int n, int ld, double c, const double *dots,
+                       hipStream_t s)
+{
+    const dim3 grid(blocks_for(n), n);
+    if (ddtype == F64)
+        hipLaunchKernelGGL(step_kernel<double>, grid, dim3(BX), 0, s, (const double *)d, ld_d, phi, n, ld, c, dots);
+    else
+        hipLaunchKernelGGL(step_kernel<float>, grid, dim3(BX), 0, s, (const float *)d, ld_d, phi, n, ld, c, dots);
+    return hipGetLastError();
+}
+
+}  // namespace px
+
+// ------------------------------------------------------------------ ABI
+
+struct px_net {
+    int device = 0;
+    px::NetState s;
+};
+
+namespace px {
+
+hipError_t net_infer(px_net *net, const double *r, int ld_r, int n, double scale, float *y, int ld_y, hipStream_t s)
+{
+    return net_forward(net->s, F64, r, ld_r, scale, y, ld_y, 1, n, n, s);
+}
+
+int net_device(const px_net *net) { return net->device; }
+
+}  // namespace px
+
+using px::set_error;
+
+namespace {
+
+constexpr long long MAX_PIXELS = 1LL << 31;
+
+int hip_err(hipError_t e, const char *what) { return set_error(PX_EHIP, "%s: %s", what, hipGetErrorString(e)); }
+
+int check_images(int batch, int H, int W)
+{
+    if (batch < 1 || H < 1 || W < 1) return set_error(PX_EINVAL, "batch, H and W must be >= 1");
+    if ((long long)batch * H * W > MAX_PIXELS) return set_error(PX_EINVAL, "more than 2^31 pixels");
+    return PX_OK;
+}
+
+int use_device(const px_net *net)
+{
+    hipError_t e = hipSetDevice(net->device);
+    return e == hipSuccess ? PX_OK : hip_err(e, "hipSetDevice");
+}
+
+}  // namespace
+
+extern "C" {
+
+int px_net_create(int device, const float *weights, px_net **out)
+{
+    if (!out) return set_error(PX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!weights) return set_error(PX_EINVAL, "weights is NULL");
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_err(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return set_error(PX_EINVAL, "device %d not present", device);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_err(e, "hipSetDevice");
+    px_net *net = new (std::nothrow) px_net;
+    if (!net) return set_error(PX_ENOMEM, "out of host memory");
+    net->device = device;
+    if ((e = px::net_alloc(net->s)) != hipSuccess || (e = px::net_set(net->s, weights)) != hipSuccess) {
+        delete net;
+        return e == hipErrorOutOfMemory ? set_error(PX_ENOMEM, "network allocation failed") : hip_err(e, "network set-up");
+    }
+    *out = net;
+    return PX_OK;
+}
+
+int px_net_destroy(px_net *net)
+{
+    if (!net) return PX_OK;
+    int st = use_device(net);
+    if (st) return st;
+    (void)hipDeviceSynchronize();
+    delete net;
+    return PX_OK;
+}
+
+int px_net_set_weights(px_net *net, const float *weights)
+{
+    if (!net || !weights) return set_error(PX_EINVAL, "net or weights is NULL");
+    int st = use_device(net);
+    if (st) return st;
+    hipError_t e = px::net_set(net->s, weights);
+    return e == hipSuccess ? PX_OK : hip_err(e, "px_net_set_weights");
+}
+
+int px_net_get_weights(px_net *net, float *weights)
+{
+    if (!net || !weights) return set_error(PX_EINVAL, "net or weights is NULL");
+    int st = use_device(net);
+    if (st) return st;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipMemcpy(weights, net->s.w, sizeof(float) * px::NPARAM, hipMemcpyDeviceToHost);
+    return e == hipSuccess ? PX_OK : hip_err(e, "px_net_get_weights");
+}
+
+int px_net_forward(px_net *net, const void *x, int x_dtype, int ldx, int batch, int H, int W, double x_scale,
+                   float *y, int ldy, void *stream)
+{
+    if (!net || !x || !y) return set_error(PX_EINVAL, "net, x or y is NULL");
+    if (x_dtype != PX_F64 && x_dtype != PX_F32) return set_error(PX_EINVAL, "x_dtype must be PX_F64 or PX_F32");
+    int st = check_images(batch, H, W);
+    if (st) return st;
+    if (ldx < W || ldy < W) return set_error(PX_EINVAL, "ldx and ldy must be >= W");
+    if (!std::isfinite(x_scale)) return set_error(PX_EINVAL, "x_scale must be finite");
+    if ((st = use_device(net))) return st;
+    hipError_t e = px::net_forward(net->s, x_dtype, x, ldx, x_scale, y, ldy, batch, H, W, (hipStream_t)stream);
+    if (e == hipErrorOutOfMemory) return set_error(PX_ENOMEM, "network workspace allocation failed");
+    return e == hipSuccess ? PX_OK : hip_err(e, "network forward launch");
+}
+
+int px_net_loss_grad(px_net *net, const float *x, const float *t, int batch, int H, int W, int loss,
+                     double *loss_out, float *grad, void *stream)
+{
+    if (!net || !x || !t) return set_error(PX_EINVAL, "net, x or t is NULL");
+    if (loss != PX_LOSS_MSE && loss != PX_LOSS_ENERGY) return set_error(PX_EINVAL, "unknown loss %d", loss);
+    int st = check_images(batch, H, W);
+    if (st) return st;
+    if ((st = use_device(net))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = px::net_gradient(net->s, x, t, batch, H, W, loss, loss_out, s);
+    if (e == hipSuccess && grad)
+        e = hipMemcpyAsync(grad, net->s.g, sizeof(float) * px::NPARAM, hipMemcpyDeviceToDevice, s);
+    if (e == hipErrorOutOfMemory) return set_error(PX_ENOMEM, "network workspace allocation failed");
+    return e == hipSuccess ? PX_OK : hip_err(e, "network gradient launch");
+}
+
+int px_net_adam(px_net *net, float lr, void *stream)
+{
+    if (!net) return set_error(PX_EINVAL, "net is NULL");
+    if (!(lr > 0.0f) || !std::isfinite(lr)) return set_error(PX_EINVAL, "lr must be finite and > 0");
+    int st = use_device(net);
+    if (st) return st;
+    hipError_t e = px::net_adam(net->s, lr, (hipStream_t)stream);
+    return e == hipSuccess ? PX_OK : hip_err(e, "Adam launch");
+}
+
+int px_net_activation(px_net *net, int layer, uint16_t *out, void *stream)
+{
+    if (!net || !out) return set_error(PX_EINVAL, "net or out is NULL");
+    if (layer < 1 || layer > 3) return set_error(PX_EINVAL, "layer must be 1, 2 or 3");
+    if (net->s.last_pixels == 0) return set_error(PX_EINVAL, "no forward pass yet");
+    int st = use_device(net);
+    if (st) return st;
+    const px::bf16 *a = layer == 1 ? net->s.a1 : layer == 2 ? net->s.a2 : net->s.a3;
+    hipError_t e = hipMemcpyAsync(out, a, sizeof(px::bf16) * px::C * (size_t)net->s.last_pixels,
+                                  hipMemcpyDeviceToDevice, (hipStream_t)stream);
+    return e == hipSuccess ? PX_OK : hip_err(e, "activation copy");
+}
+
+}  // extern "C"

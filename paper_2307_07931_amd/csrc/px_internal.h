@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+struct px_net;
+
 namespace px {
 
 enum Dtype { F64 = 0, F32 = 1, BF16 = 2 };
@@ -128,5 +130,26 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
 int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, int bc, double rtol,
                 int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, BatchStat *stats,
                 hipStream_t user_stream, char *err, size_t errlen);
+
+// ---- learned correction (net.hip)
+// Records the message of a failing ABI call (px_last_error) and returns code.
+int set_error(int code, const char *fmt, ...);
+// y (FP32, rows of ld_y) = N(r * scale) for one n x n image r (FP64, rows of ld_r).
+hipError_t net_infer(px_net *net, const double *r, int ld_r, int n, double scale, float *y, int ld_y,
+                     hipStream_t s);
+int net_device(const px_net *net);
+// Training pair pieces: sums[0] = sum S(phi)^2, sums[1] = sum e^2 (loss MSE) or sum e K e
+// (loss ENERGY), e = -phi; then x = -S(phi) / rms, t = e / rms.  part: >= pair_num_blocks(n)
+// double2 slots.
+int pair_num_blocks(int n);
+hipError_t pair_launch(const double *phi, int n, int ld, int loss, float *x, float *t, double *part,
+                       double *sums, hipStream_t s);
+// Step of the learned refinement: dots = {<r, d>, <d, S d>} (S with odd reflection, d
+// compact n x ld_d, FP32 or FP64), then phi += a d with a = dots[0] / (c dots[1]) (0 when
+// dots[1] == 0).  part: >= pair_num_blocks(n) double2 slots.
+hipError_t dots_launch(int ddtype, const void *d, int ld_d, const double *r, int ld_r, int n, double *part,
+                       double *dots, hipStream_t s);
+hipError_t step_launch(int ddtype, const void *d, int ld_d, double *phi, int n, int ld, double c,
+                       const double *dots, hipStream_t s);
 
 }  // namespace px

@@ -199,3 +199,61 @@ def test_batched_validation(ctx):
     o = px._SolveOpts(px.SOLVE_MIXED_F32, 3, 1e-8, 100, 0, 8, 0, 0)
     assert L.px_solve_batched(probs, 2, ctypes.byref(o), st, ctx, None) == px.EINVAL
     assert L.px_solve_batched(probs, 2, None, st, ctx, None) == px.EINVAL
+
+
+def test_net_validation(ctx):
+    L = px.lib()
+    P = ctypes.c_void_p
+    h = ctypes.c_void_p()
+    assert L.px_net_create(0, None, ctypes.byref(h)) == px.EINVAL
+    assert "NULL" in px.last_error()
+    w = (ctypes.c_float * px.NET_NPARAM)()
+    assert L.px_net_create(0, w, None) == px.EINVAL
+    assert L.px_net_destroy(None) == px.OK
+    assert L.px_net_set_weights(None, w) == px.EINVAL
+    assert L.px_net_get_weights(None, w) == px.EINVAL
+    assert L.px_net_forward(None, P(FAKE), px.F32, 8, 1, 8, 8, 1.0, P(FAKE2), 8, None) == px.EINVAL
+    assert L.px_net_loss_grad(None, P(FAKE), P(FAKE2), 1, 8, 8, 0, None, None, None) == px.EINVAL
+    assert L.px_net_adam(None, ctypes.c_float(1e-3), None) == px.EINVAL
+    assert L.px_net_activation(None, 1, P(FAKE), None) == px.EINVAL
+    # training pairs: size, pointers, loss kind, overlap
+    mk = lambda **kw: L.px_net_make_pair(P(kw.get("phi", FAKE)), kw.get("n", 64), kw.get("ld", 66),
+                                         kw.get("loss", 0), P(kw.get("x", FAKE2)), P(kw.get("t", FAKE2 * 2)),
+                                         ctx, None)
+    assert mk(n=0) == px.EINVAL
+    assert mk(ld=65) == px.EINVAL
+    assert mk(phi=0) == px.EINVAL
+    assert mk(x=0) == px.EINVAL
+    assert mk(loss=7) == px.EINVAL
+    assert mk(x=FAKE + 8) == px.EALIAS
+    assert mk(t=FAKE2 + 64) == px.EALIAS
+
+
+def test_solve_learned_validation(ctx):
+    L = px.lib()
+    P = ctypes.c_void_p
+
+    def run(opts=True, net=None, **kw):
+        o = px._LearnedOpts(kw.get("norm", 0), kw.get("rtol", 1e-10), kw.get("max_sweeps", 100),
+                            kw.get("smooth", 16), kw.get("tblock", 0), kw.get("use_net", 0))
+        return L.px_solve_learned(P(kw.get("phi", FAKE)), kw.get("n", 64), kw.get("ld", 66),
+                                  P(kw.get("f", FAKE2)), kw.get("ld_f", 64), kw.get("h", 1 / 64),
+                                  kw.get("lam", 1e-5), net, ctypes.byref(o) if opts else None, None,
+                                  kw.get("ctx", ctx), None)
+
+    assert run(opts=False) == px.EINVAL
+    assert run(ctx=None) == px.EINVAL
+    assert run(n=0) == px.EINVAL
+    assert run(phi=0) == px.EINVAL
+    assert run(f=0) == px.EINVAL
+    assert run(h=0.0) == px.EINVAL
+    assert run(lam=-1.0) == px.EINVAL
+    assert run(rtol=float("nan")) == px.EINVAL
+    assert run(norm=2) == px.EINVAL
+    assert run(max_sweeps=-1) == px.EINVAL
+    assert run(smooth=0) == px.EINVAL
+    assert run(tblock=9) == px.EINVAL
+    assert run(use_net=2) == px.EINVAL
+    assert run(use_net=1) == px.EINVAL  # no network
+    assert "network" in px.last_error()
+    assert run(f=FAKE + 8) == px.EALIAS

@@ -53,18 +53,31 @@ def uniform_rhs(n: int, seed: int) -> np.ndarray:
     return rng(seed).uniform(-1.0, 1.0, size=(n, n))
 
 
-def grf_rhs(n: int, seed: int) -> np.ndarray:
-    """Gaussian random field with power spectrum ~ |k|^-2, zero on the boundary
-    in the sense of the sine basis: f = sum_pq xi_pq / |k_pq| * mode_pq with
-    xi ~ N(0,1) from PCG64(seed), modes the cell-centred sine modes
-    sin(p pi x) sin(q pi y), p, q = 1..n (orthonormal DST-II synthesis).
-    Normalised to unit root-mean-square."""
+def grf_field(n: int, seed: int, power: float) -> np.ndarray:
+    """Gaussian random field with amplitude spectrum |k|^-power in the cell-centred
+    sine basis: sum_pq xi_pq |k_pq|^-power sin(p pi x) sin(q pi y), xi ~ N(0,1) from
+    PCG64(seed), p, q = 1..n (orthonormal DST-II synthesis), normalised to unit
+    root-mean-square.  It vanishes at the cell faces of the boundary in the sense of
+    the sine basis."""
     xi = rng(seed).standard_normal(size=(n, n))
     p = np.arange(1, n + 1, dtype=np.float64)
-    amp = 1.0 / np.sqrt(p[:, None] ** 2 + p[None, :] ** 2)
+    k2 = p[:, None] ** 2 + p[None, :] ** 2
+    amp = 1.0 / np.sqrt(k2) if power == 1.0 else k2 ** (-0.5 * power)
     f = _fft.idstn(xi * amp, type=2, norm="ortho", workers=-1)
     f /= np.sqrt(np.mean(f * f))
     return f
+
+
+def grf_rhs(n: int, seed: int) -> np.ndarray:
+    """Right-hand side with power spectrum ~ |k|^-2 (amplitude |k|^-1): grf_field with
+    power 1."""
+    return grf_field(n, seed, 1.0)
+
+
+def error_field(n: int, seed: int) -> np.ndarray:
+    """Initial error of a training solve: amplitude spectrum |k|^-3, the spectrum of the
+    solution of L u = f for f from grf_rhs (the Laplacian's symbol grows as |k|^2)."""
+    return grf_field(n, seed, 3.0)
 
 
 def sine_mode(n: int, p: int, q: int, node_centred: bool = False) -> np.ndarray:
