@@ -137,6 +137,25 @@ def cpu_baseline(sample_sweeps):
                       f"(of the {SWEEPS}), plain three-pass oracle, single thread, {t:.1f} s"}
 
 
+def exact_solution(f):
+    """The exact discrete solution of L u = f (5-point Laplacian / h^2, cell-centred,
+    homogeneous Dirichlet by odd reflection) by the type-II sine transform, which
+    diagonalises L: used to state the error of each result."""
+    import numpy as np
+    from scipy import fft as sfft
+    n = f.shape[0]
+    k = np.arange(1, n + 1, dtype=np.float64)
+    lam = -4.0 * n * n * np.sin(k * np.pi / (2 * n)) ** 2
+    return sfft.idstn(sfft.dstn(f, type=2, norm="ortho") / (lam[:, None] + lam[None, :]), type=2, norm="ortho")
+
+
+def slowest_mode_factor(n):
+    """Per-sweep damping of the smoothest error mode under damped Jacobi (omega = 2/3):
+    1 - omega * (sin^2(pi/2n) + sin^2(pi/2n))."""
+    import math
+    return 1.0 - OMEGA * 2.0 * math.sin(math.pi / (2 * n)) ** 2
+
+
 def mixed_workload(px, ctx):
     """Mixed-precision refinement (FP32 / BF16 inner sweeps, FP64 outer residual and
     update) against plain FP64 relaxation, on |k|^-2 Gaussian-random-field right-hand
@@ -148,11 +167,10 @@ def mixed_workload(px, ctx):
     import numpy as np
     import torch
     import workloads as W
-    from oracle import exact  # CPU reference for the error of each result
     out = {"solves": [], "per_sweep_8192": {}}
     for n in (256, 512):
         f_host = W.grf_rhs(n, W.SEED_GRF_8192)
-        ex = exact.dst_solve(f_host, 1.0 / n)
+        ex = exact_solution(f_host)
         h = 1.0 / n
         lam = OMEGA * h * h / 4.0
         for mode, name, inner in ((px.SOLVE_PLAIN, "plain_f64", 0), (px.SOLVE_MIXED_F32, "mixed_f32", 64),
@@ -197,7 +215,7 @@ def mixed_workload(px, ctx):
                       raise_on_error=False)
         per["mixed_" + ("f32" if mode == px.SOLVE_MIXED_F32 else "bf16")] = {
             "s_per_sweep_incl_refine": st.seconds / st.sweeps, "inner": inner, "outer_steps": st.outer_steps}
-    g = exact.mode_factor(n, 1, 1, OMEGA)
+    g = slowest_mode_factor(n)
     floor = 5.6e-10  # FP64 attainable relative residual for this field at 8192^2 (exact solution rounded)
     tau = max(1e-10, 4 * floor)
     sweeps = math.log(tau) / math.log(g)
@@ -213,6 +231,178 @@ def mixed_workload(px, ctx):
     return out
 
 
+def _fresh(px, n, f_host):
+    import torch
+    phi = px.alloc_grid(n, torch.float64)
+    f = px.alloc_rhs(n, torch.float64)
+    f[:, :n] = torch.from_numpy(f_host).cuda()
+    return phi, f
+
+
+def _run_method(px, ctx, net, method, n, f_host, smooth, max_sweeps, rtol=1e-10):
+    """One solve of L phi = f from phi = 0: plain FP64 relaxation, or the refinement loop
+    with (net) or without (nonet) the network.  Returns the stats."""
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    phi, f = _fresh(px, n, f_host)
+    if method == "plain":
+        return px.solve(phi, n, f, h, lam, ctx, mode=px.SOLVE_PLAIN, rtol=rtol, check_every=max(smooth, 256),
+                        max_sweeps=max_sweeps, raise_on_error=False)
+    return px.solve_learned(phi, n, f, h, lam, ctx, net=net, use_net=(method == "net"), rtol=rtol,
+                            smooth_sweeps=smooth, max_sweeps=max_sweeps, raise_on_error=False)
+
+
+def _seconds_per_sweep(px, ctx, net, method, n, f_host, smooth, budget=4096):
+    """Wall time per sweep of a budget-limited solve (checks, corrections and network
+    evaluations included), from two budgets so that set-up time cancels."""
+    s1 = _run_method(px, ctx, net, method, n, f_host, smooth, budget // 4, rtol=0.0)
+    s2 = _run_method(px, ctx, net, method, n, f_host, smooth, budget, rtol=0.0)
+    return (s2.seconds - s1.seconds) / (s2.sweeps - s1.sweeps)
+
+
+def learned_workload(px, ctx, train_steps, train_n=1024, eval_n=2048):
+    """Learned correction network (4 layers of 3x3 conv, 32 channels, BF16 weights and
+    activations, FP32 accumulation) trained on the GPU on (residual, error) pairs of
+    plain solves at train_n^2 (initial errors with the |k|^-3 spectrum of L^-1 f for
+    |k|^-2 Gaussian-random-field f), then used in the refinement loop (FP64 residual,
+    energy-optimal step along the network's direction, plain smoothing sweeps, plain
+    relaxation as judge and fallback).  Compared with the same loop without the network
+    and with plain FP64 relaxation: measured time to max|r| <= 1e-10 max|f| at 256^2,
+    512^2 and 1024^2 on unseen seeds, and at eval_n^2 extrapolated (sweeps from 1024^2
+    scaled by n^2, seconds per sweep measured at eval_n^2)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2307_07931_amd import learned
+    out = {}
+    t0 = time.perf_counter()
+    fields = [W.error_field(train_n, W.SEED_TRAIN_BASE + s) for s in range(8)]
+    X, T = learned.training_pairs(fields, ctx)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net = px.Net(W.net_initial_weights(W.SEED_TRAIN_BASE))
+    t1 = time.perf_counter()
+    hist = learned.train(net, X, T, steps=train_steps, batch=2, lr=2e-3, log_every=max(1, train_steps // 10))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    out["training"] = {"n": train_n, "pairs": int(X.shape[0]), "steps": train_steps, "batch": 2,
+                       "loss_history": hist, "seconds_pairs": round(t_pairs, 2), "seconds_train": round(t_train, 2)}
+    log(f"  learned: {X.shape[0]} pairs in {t_pairs:.1f} s, {train_steps} steps in {t_train:.1f} s, loss {hist[0][1]:.3g} -> {hist[-1][1]:.3g}")
+    del X, T
+    torch.cuda.empty_cache()
+    measured = []
+    for n in (256, 512, 1024):
+        f_host = W.grf_rhs(n, W.SEED_EVAL_BASE + 1)
+        ex = exact_solution(f_host)
+        for method, smooth in (("plain", 1024), ("nonet", 16), ("nonet", 64), ("net", 16), ("net", 64)):
+            phi, f = _fresh(px, n, f_host)
+            h = 1.0 / n
+            lam = OMEGA * h * h / 4.0
+            if method == "plain":
+                st = px.solve(phi, n, f, h, lam, ctx, mode=px.SOLVE_PLAIN, rtol=1e-10, check_every=smooth,
+                              raise_on_error=False)
+            else:
+                st = px.solve_learned(phi, n, f, h, lam, ctx, net=net, use_net=(method == "net"), rtol=1e-10,
+                                      smooth_sweeps=smooth, raise_on_error=False)
+            err = float(np.abs(phi[1:n + 1, 1:n + 1].cpu().numpy() - ex).max() / np.abs(ex).max())
+            rec = {"n": n, "method": method, "smooth": smooth, "status": st.status, "sweeps": st.sweeps,
+                   "seconds": round(st.seconds, 4), "rel_res_max": st.rel_res_max, "rel_err_vs_exact": err}
+            if method == "net":
+                rec["corrections"], rec["fell_back"] = st.corrections, st.fell_back
+            measured.append(rec)
+            log(f"  learned/{n}: {rec}")
+    out["measured"] = measured
+    # eval_n^2: sweeps to the tolerance scale as n^2 for every local method here (their
+    # per-sweep reduction of the smoothest error is proportional to h^2); measured per
+    # method at 1024^2, times 4 per doubling of n, times the measured s/sweep at eval_n
+    f_host = W.grf_rhs(eval_n, W.SEED_EVAL_BASE)
+    extra = []
+    for r in measured:
+        if r["n"] != 1024:
+            continue
+        sps = _seconds_per_sweep(px, ctx, net, r["method"], eval_n, f_host, r["smooth"])
+        sweeps = r["sweeps"] * (eval_n / 1024) ** 2
+        rec = {"method": r["method"], "smooth": r["smooth"], "s_per_sweep": sps, "extrapolated_sweeps": sweeps,
+               "extrapolated_seconds": sweeps * sps}
+        extra.append(rec)
+        log(f"  learned/{eval_n}: {rec}")
+    out["extrapolated_" + str(eval_n)] = extra
+    best = {m: min(r["extrapolated_seconds"] for r in extra if r["method"] == m) for m in ("plain", "nonet", "net")}
+    out["speedup_vs_plain"] = {m: best["plain"] / best[m] for m in ("nonet", "net")}
+    out["gain_net_vs_nonet"] = best["nonet"] / best["net"]
+    meas = {m: min(r["seconds"] for r in measured if r["method"] == m and r["n"] == 1024) for m in ("plain", "nonet", "net")}
+    out["measured_speedup_vs_plain_1024"] = {m: meas["plain"] / meas[m] for m in ("nonet", "net")}
+    net.close()
+    return out
+
+
+def batched_workload(px, ctx, count=512, solve_count=64):
+    """Batches of uneven problems (sizes drawn from {64,...,1024}, f ~ U[-1,1]): (a) 64
+    FP32 sweeps of all `count` problems in one persistent launch per block of sweeps,
+    against one px_relax_fused call per problem; (b) FP64 refinement around FP32 sweeps to
+    max|r| <= 1e-8 max|f| of the first solve_count problems of size <= 256, as one
+    graph-replayed batch against one px_solve per problem."""
+    import numpy as np
+    import torch
+    import workloads as W
+    sizes = W.batch_sizes(count)
+    out = {"count": count, "sizes": {int(k): int(v) for k, v in zip(*np.unique(sizes, return_counts=True))}}
+    items, cells = [], 0
+    for i, n in enumerate(sizes):
+        n = int(n)
+        h = 1.0 / n
+        phi = px.alloc_grid(n, torch.float32)
+        f = px.alloc_rhs(n, torch.float32)
+        f[:, :n] = torch.from_numpy(W.uniform_rhs(n, W.SEED_BATCH_BASE + i)).cuda().float()
+        items.append((phi, f, n, h, OMEGA * h * h / 4.0))
+        cells += n * n
+    sweeps = 64
+    tb = time_region(lambda: px.relax_batched(items, sweeps, ctx, resmode=px.RES_NONE), reps=3, warmup=1)
+    scratch = {}
+
+    def sequential():
+        for phi, f, n, h, lam in items:
+            if n not in scratch:
+                scratch[n] = px.alloc_grid(n, torch.float32)
+            px.relax_fused(phi, scratch[n], n, f, h, lam, sweeps, ctx, resmode=px.RES_NONE)
+    ts = time_region(sequential, reps=3, warmup=1)
+    out["relax"] = {"sweeps": sweeps, "cells": cells, "batched_s": tb / 3, "sequential_s": ts / 3,
+                    "batched_gcell_s": cells * sweeps * 3 / tb / 1e9,
+                    "sequential_gcell_s": cells * sweeps * 3 / ts / 1e9, "speedup": ts / tb}
+    log(f"  batched relax: {out['relax']}")
+    del items, scratch
+    torch.cuda.empty_cache()
+    small = [(i, int(n)) for i, n in enumerate(sizes) if n <= 256][:solve_count]
+
+    def build():
+        its = []
+        for i, n in small:
+            h = 1.0 / n
+            phi = px.alloc_grid(n, torch.float64)
+            f = px.alloc_rhs(n, torch.float64)
+            f[:, :n] = torch.from_numpy(W.uniform_rhs(n, W.SEED_BATCH_BASE + i)).cuda()
+            its.append((phi, f, n, h, OMEGA * h * h / 4.0))
+        return its
+    its = build()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, stats = px.solve_batched(its, ctx, mode=px.SOLVE_MIXED_F32, rtol=1e-8, raise_on_error=False)
+    t_batch = time.perf_counter() - t0
+    its2 = build()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [px.solve(phi, n, f, h, lam, ctx, mode=px.SOLVE_MIXED_F32, rtol=1e-8, raise_on_error=False)
+           for phi, f, n, h, lam in its2]
+    t_seq = time.perf_counter() - t0
+    same = all(torch.equal(a[0], b[0]) for a, b in zip(its, its2))
+    out["solve"] = {"problems": len(small), "sizes": sorted({n for _, n in small}), "rtol": 1e-8,
+                    "status": status, "batched_s": t_batch, "sequential_s": t_seq, "speedup": t_seq / t_batch,
+                    "max_rel_res": max(s.rel_res_max for s in stats), "results_identical_to_sequential": same,
+                    "total_sweeps": int(sum(s.sweeps for s in stats))}
+    log(f"  batched solve: {out['solve']}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,12 +414,14 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (the known-size kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=["relax", "mixed"], default="relax",
+    ap.add_argument("--workload", choices=["relax", "mixed", "learned", "batched"], default="relax",
                     help="relax: the fused relaxation benchmark (default); mixed: mixed-precision "
-                         "refinement against plain FP64 (time to tolerance)")
+                         "refinement against plain FP64 (time to tolerance); learned: the trained "
+                         "correction network in the refinement loop; batched: 512 uneven problems")
+    ap.add_argument("--train-steps", type=int, default=1000)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=24)
+    ap.add_argument("--cpu-sweeps", type=int, default=SWEEPS)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the relaxation is sharded "
@@ -261,6 +453,20 @@ def main():
         print(json.dumps({"metric": METRIC, "workload": "mixed_precision_refinement_grf",
                           "value": round(p8["mixed_f32"]["speedup_vs_plain_f64"], 3),
                           "unit": "x time-to-tolerance speedup (mixed FP32 vs plain FP64, 8192^2, extrapolated)",
+                          "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "results": res,
+                          "wall_s": round(time.perf_counter() - t0, 1)}), flush=True)
+        ctx.close()
+        return
+
+    if args.workload in ("learned", "batched"):
+        t0 = time.perf_counter()
+        if args.workload == "learned":
+            res = learned_workload(px, ctx, args.train_steps)
+            value, unit = res["speedup_vs_plain"]["net"], "x time-to-1e-10 speedup (learned loop vs plain FP64, 2048^2, extrapolated)"
+        else:
+            res = batched_workload(px, ctx)
+            value, unit = res["solve"]["speedup"], "x speedup (one batched solve vs per-problem solves)"
+        print(json.dumps({"metric": METRIC, "workload": args.workload, "value": round(value, 3), "unit": unit,
                           "higher_is_better": True, "n_gpus": 1, "data": "synthetic", "results": res,
                           "wall_s": round(time.perf_counter() - t0, 1)}), flush=True)
         ctx.close()

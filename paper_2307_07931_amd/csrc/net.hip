@@ -42,6 +42,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float bfv(bf16 x) { return bf16_to_f32(x.bits); }
 __device__ __forceinline__ bf16 tobf(float x) { return bf16{f32_to_bf16_rne(x)}; }
+// ReLU that keeps NaN (as max(x, 0) of IEEE propagation would): a broken network stays visible.
+__device__ __forceinline__ float relu(float x) { return x < 0.0f ? 0.0f : x; }
 
 // tap t = 3a + c reads offset (a - 1, c - 1); the transposed convolution reads (1 - a, 1 - c)
 __device__ __forceinline__ int tap_dy(int t, bool mirror) { return mirror ? 1 - t / 3 : t / 3 - 1; }
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, in
         float acc = 0.0f;
 #pragma unroll
         for (int t = 0; t < 9; ++t) acc += bfv(w1[co * 9 + t]) * xv[t];
-        out[co] = tobf(fmaxf(acc, 0.0f));
+        out[co] = tobf(relu(acc));
     }
     uint4 *dst = reinterpret_cast<uint4 *>(a1 + p * C);
 #pragma unroll
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(BX) void conv32_mfma_kernel(const bf16 *__restrict_
         for (int e = 0; e < 4; ++e) {
             float a = acc[4 * g + e];
             if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
-            else a = fmaxf(a, 0.0f);
+            else a = relu(a);
             v[e] = f32_to_bf16_rne(a);
         }
         uint2 pk;
