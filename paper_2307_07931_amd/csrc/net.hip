@@ -106,60 +106,95 @@ __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, in
     for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(out)[q];
 }
 
-// 32 -> 32 convolution on the matrix cores.  One wave: 32 output channels x 32 pixels
-// (j0 .. j0+31 of row i of image b).  A = weights (rows: output channel, k: input
-// channel within a tap), B = input patches (k: input channel, columns: pixels).
-// MIRROR computes the input gradient: in = gradient of the layer output, weights in
-// [t][ci][co] order, taps mirrored, and the result is multiplied by the ReLU mask of
-// `mask` (the layer's input activation).  Otherwise the epilogue applies ReLU.
+// 32 -> 32 convolution on the matrix cores, as an implicit GEMM per output tile.
+//
+// A block (4 waves) owns TROWS = 4 image rows x TPX = 64 pixels; wave w computes row
+// i0 + w, as two 32-pixel halves.  The block stages the input patch it needs
+// ((TROWS + 2) x (TPX + 2) pixels x 32 channels) and the layer's weights (9 taps x 32 x
+// 32) in LDS once, then each wave runs 9 taps x 2 channel halves x 2 pixel halves = 36
+// v_mfma_f32_32x32x16_bf16: A = weights (rows: output channel, k: input channel of the
+// tap), B = patch pixels (k: input channel, columns: pixel), operands read from LDS with
+// 16-byte loads.  Pixels and weight rows are padded to PSTR = 40 elements (80 bytes) so
+// that the 16-byte reads of neighbouring lanes fall in different LDS banks.  Blocks
+// loop over tiles so the weights are loaded once per block.
+//
+// MIRROR computes the input gradient: `in` is the gradient of the layer output, the
+// weights are in [t][ci][co] order, the taps are mirrored, and the result is multiplied
+// by the ReLU mask of `mask` (the layer's input activation).  Otherwise the epilogue
+// applies ReLU.  Outputs are rounded to BF16 and stored channels-last.
+constexpr int TROWS = 4, TPX = 64, PSTR = 40;
+constexpr int PROWS = TROWS + 2, PCOLS = TPX + 2;
+
 template <bool MIRROR>
-__global__ __launch_bounds__(BX) void conv32_mfma_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wl,
-                                                         bf16 *__restrict__ out, const bf16 *__restrict__ mask,
-                                                         int B, int H, int W)
+__global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wl,
+                                                    bf16 *__restrict__ out, const bf16 *__restrict__ mask, int B,
+                                                    int H, int W)
 {
-    const int lane = threadIdx.x & 63;
-    const int tiles_w = (W + 31) / 32;
-    const long long wave = (long long)blockIdx.x * (BX / 64) + (threadIdx.x >> 6);
-    if (wave >= (long long)B * H * tiles_w) return;
-    const int tj = (int)(wave % tiles_w), i = (int)((wave / tiles_w) % H), b = (int)(wave / ((long long)tiles_w * H));
-    const int n = lane & 31, kg = lane >> 5;
-    const int j = tj * 32 + n;
-    f32x16 acc = {};
-#pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int ii = i + tap_dy(t, MIRROR), jj = j + tap_dx(t, MIRROR);
-        const bool ok = ii >= 0 && ii < H && jj >= 0 && jj < W;
-        const long long src = ok ? (((long long)b * H + ii) * W + jj) * C : 0;
-#pragma unroll
-        for (int c16 = 0; c16 < 2; ++c16) {
-            const int k0 = c16 * 16 + kg * 8;
-            uint4 bu = *reinterpret_cast<const uint4 *>(in + src + k0);
-            if (!ok) bu = make_uint4(0, 0, 0, 0);
-            const uint4 au = *reinterpret_cast<const uint4 *>(wl + (t * C + n) * C + k0);
-            bf16x8 av, bv;
-            __builtin_memcpy(&av, &au, 16);
-            __builtin_memcpy(&bv, &bu, 16);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
-        }
+    __shared__ __align__(16) bf16 sw[9 * C * PSTR];
+    __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int q = tid; q < 9 * C * 4; q += BX) {
+        const int row = q >> 2, ch = q & 3;
+        *reinterpret_cast<uint4 *>(sw + row * PSTR + ch * 8) = *reinterpret_cast<const uint4 *>(wl + row * C + ch * 8);
     }
-    if (j >= W) return;
-    const long long p = ((long long)b * H + i) * W + j;
-    // lane holds output channels 8g + 4*kg + e (e = 0..3) of pixel j, in acc[4g + e]
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-        const int co = 8 * g + 4 * kg;
-        unsigned short v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            float a = acc[4 * g + e];
-            if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
-            else a = relu(a);
-            v[e] = f32_to_bf16_rne(a);
+    const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
+    const long long ntiles = (long long)B * tiles_h * tiles_w;
+    const int n = lane & 31, kg = lane >> 5;
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tw = (int)(tile % tiles_w), th = (int)((tile / tiles_w) % tiles_h);
+        const int b = (int)(tile / ((long long)tiles_w * tiles_h));
+        const int i0 = th * TROWS, j0 = tw * TPX;
+        __syncthreads();  // the previous tile's LDS reads are done (first pass: weights stored)
+        for (int q = tid; q < PROWS * PCOLS * 4; q += BX) {
+            const int ch = q & 3, pc = (q >> 2) % PCOLS, pr = (q >> 2) / PCOLS;
+            const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (ii >= 0 && ii < H && jj >= 0 && jj < W)
+                v = *reinterpret_cast<const uint4 *>(in + (((long long)b * H + ii) * W + jj) * C + ch * 8);
+            *reinterpret_cast<uint4 *>(sp + (pr * PCOLS + pc) * PSTR + ch * 8) = v;
         }
-        uint2 pk;
-        pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
-        pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
-        *reinterpret_cast<uint2 *>(out + p * C + co) = pk;
+        __syncthreads();
+        f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int pr = wv + 1 + tap_dy(t, MIRROR), pc = n + 1 + tap_dx(t, MIRROR);
+#pragma unroll
+            for (int c16 = 0; c16 < 2; ++c16) {
+                const int k0 = c16 * 16 + kg * 8;
+                bf16x8 av, b0, b1;
+                __builtin_memcpy(&av, sw + (t * C + n) * PSTR + k0, 16);
+                __builtin_memcpy(&b0, sp + (pr * PCOLS + pc) * PSTR + k0, 16);
+                __builtin_memcpy(&b1, sp + (pr * PCOLS + pc + 32) * PSTR + k0, 16);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+            }
+        }
+        const int i = i0 + wv;
+        if (i >= H) continue;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            const int j = j0 + half * 32 + n;
+            if (j >= W) continue;
+            const f32x16 &acc = half ? acc1 : acc0;
+            const long long p = ((long long)b * H + i) * W + j;
+            // lane holds output channels 8g + 4 kg + e (e = 0..3) of pixel j in acc[4g + e]
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int co = 8 * g + 4 * kg;
+                unsigned short v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    float a = acc[4 * g + e];
+                    if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
+                    else a = relu(a);
+                    v[e] = f32_to_bf16_rne(a);
+                }
+                uint2 pk;
+                pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
+                pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
+                *reinterpret_cast<uint2 *>(out + p * C + co) = pk;
+            }
+        }
     }
 }
 
@@ -563,7 +598,8 @@ hipError_t net_workspace(NetState &s, long long pixels)
 
 unsigned conv_blocks(int B, int H, int W)
 {
-    return (unsigned)(((long long)B * H * ((W + 31) / 32) + (BX / 64) - 1) / (BX / 64));
+    const long long tiles = (long long)B * ((H + TROWS - 1) / TROWS) * ((W + TPX - 1) / TPX);
+    return (unsigned)std::min<long long>(tiles, 2048);  // 8 blocks per CU; blocks loop over tiles
 }
 
 // Forward pass: y (rows of ldy) = N(x * scale); x rows of ldx, FP64 or FP32.
@@ -579,9 +615,9 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
     else
         hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(blocks_for(N)), dim3(BX), 0, st, (const float *)x, ldx, scale,
                            s.nw.w1, s.a1, B, H, W);
-    hipLaunchKernelGGL(conv32_mfma_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a1, s.nw.w2f, s.a2,
+    hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a1, s.nw.w2f, s.a2,
                        (const bf16 *)nullptr, B, H, W);
-    hipLaunchKernelGGL(conv32_mfma_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
+    hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
                        (const bf16 *)nullptr, B, H, W);
     hipLaunchKernelGGL(l4_fwd_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
     s.last_pixels = N;
@@ -615,12 +651,12 @@ hipError_t net_gradient(NetState &s, const float *x, const float *t, int B, int 
     hipLaunchKernelGGL(wgrad32_kernel, dim3(WG_BLOCKS), dim3(BX), 0, st, s.a2, s.dz3, s.part, B, H, W);
     hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW2,
                        s.g + OFF3);
-    hipLaunchKernelGGL(conv32_mfma_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz3, s.nw.w3b, s.dz2, s.a2, B, H, W);
+    hipLaunchKernelGGL(conv32_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz3, s.nw.w3b, s.dz2, s.a2, B, H, W);
     // layer 2
     hipLaunchKernelGGL(wgrad32_kernel, dim3(WG_BLOCKS), dim3(BX), 0, st, s.a1, s.dz2, s.part, B, H, W);
     hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW2,
                        s.g + OFF2);
-    hipLaunchKernelGGL(conv32_mfma_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz2, s.nw.w2b, s.dz1, s.a1, B, H, W);
+    hipLaunchKernelGGL(conv32_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz2, s.nw.w2b, s.dz1, s.a1, B, H, W);
     // layer 1
     hipLaunchKernelGGL(wgrad1_kernel, dim3(WG_BLOCKS), dim3(NW1), 0, st, x, W, s.dz1, s.part, B, H, W);
     hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW1)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW1, s.g);

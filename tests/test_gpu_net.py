@@ -257,7 +257,7 @@ def test_training_reduces_loss_and_trained_net_converges(ctx):
     X, T = learned.training_pairs(fields, ctx, snapshots=(16, 64, 256, 1024))
     assert X.shape == (16, n, n) and torch.isfinite(X).all() and torch.isfinite(T).all()
     # normalisation: unit root-mean-square
-    assert torch.allclose((X.double() ** 2).mean(dim=(1, 2)), torch.ones(16, dtype=torch.float64), rtol=1e-5)
+    assert torch.allclose((X.double() ** 2).mean(dim=(1, 2)).cpu(), torch.ones(16, dtype=torch.float64), rtol=1e-5)
     net = px.Net(W.net_initial_weights(24))
     log = learned.train(net, X, T, steps=300, batch=4, lr=2e-3, log_every=50)
     first, last = log[0][1], np.mean([v for _, v in log[-2:]])
