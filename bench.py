@@ -37,7 +37,32 @@ BYTES_PER_CELL = {"f64": 24, "f32": 12, "bf16": 6}  # read phi + f, write phi', 
 # (the 78.6 TFLOP/s figure counts an FMA as two).
 FLOPS_PER_CELL_SWEEP = 9
 FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
+# HBM traffic of the FP64 fused relaxation at 4096^2, per launch: rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE (KiB per dispatch, averaged over the dispatches of a short bench run with
+# the given sweeps per launch and tile rows), scaled by what the same counters read for a
+# 1 GiB device-to-device copy (FETCH_SIZE 524302.76 KiB -> x 1048576 / 524302.76,
+# WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
+# (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
+TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
+TRAFFIC_SHA256 = "6aab2985c41c23025e537a846a976322ac3b79473b759d7cec3e867bbf4b43a1"
+TRAFFIC_SCALE = (1048576.0 / 524302.76, 1.0)
+TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
+    (8, 16): (272325.66, 131286.32), (8, 20): (247775.35, 131283.18), (8, 24): (230834.62, 131280.91),
+    (8, 28): (219077.19, 131279.61), (8, 32): (208242.93, 131278.29), (1, 16): (167072.05, 132517.95),
+}
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
+
+
+def measured_traffic(k, rows):
+    """HBM bytes per launch of the FP64 relaxation at 4096^2 from the counter table, or
+    None if the kernel sources changed since it was taken or the configuration is absent."""
+    import hashlib
+    src = b"".join(open(os.path.join(ROOT, "paper_2307_07931_amd", "csrc", f), "rb").read()
+                   for f in TRAFFIC_SOURCES)
+    if hashlib.sha256(src).hexdigest() != TRAFFIC_SHA256 or (k, rows) not in TRAFFIC_KIB:
+        return None
+    fk, wk = TRAFFIC_KIB[(k, rows)]
+    return {"read": fk * 1024 * TRAFFIC_SCALE[0], "write": wk * 1024 * TRAFFIC_SCALE[1]}
 
 
 def log(*a):
@@ -204,17 +229,20 @@ def mixed_workload(px, ctx):
                    "gcell_s": round(n * n * 64 * 5 / t / 1e9, 1)}
         del a, b, f, src
         torch.cuda.empty_cache()
-    # refinement step (FP64 residual + update + rounding of r) at 8192^2: one mixed solve
-    # with a budget of one outer step, timed on the host
+    # mixed solves at 8192^2 with budgets of 4 and 12 outer steps: the difference gives the
+    # time per inner sweep including the FP64 refinement step, without set-up costs
     phi = px.alloc_grid(n, torch.float64)
     f = px.alloc_rhs(n, torch.float64)
     f[:, :n] = torch.from_numpy(f_host).cuda()
     for inner, mode in ((64, px.SOLVE_MIXED_F32), (32, px.SOLVE_MIXED_BF16)):
-        phi.zero_()
-        st = px.solve(phi, n, f, h, lam, ctx, mode=mode, rtol=0.0, max_sweeps=inner * 4, inner_sweeps=inner,
-                      raise_on_error=False)
+        secs = []
+        for steps in (4, 12):
+            phi.zero_()
+            st = px.solve(phi, n, f, h, lam, ctx, mode=mode, rtol=0.0, max_sweeps=inner * steps,
+                          inner_sweeps=inner, check_every=inner * steps, raise_on_error=False)
+            secs.append((st.seconds, st.sweeps))
         per["mixed_" + ("f32" if mode == px.SOLVE_MIXED_F32 else "bf16")] = {
-            "s_per_sweep_incl_refine": st.seconds / st.sweeps, "inner": inner, "outer_steps": st.outer_steps}
+            "s_per_sweep_incl_refine": (secs[1][0] - secs[0][0]) / (secs[1][1] - secs[0][1]), "inner": inner}
     g = slowest_mode_factor(n)
     floor = 5.6e-10  # FP64 attainable relative residual for this field at 8192^2 (exact solution rounded)
     tau = max(1e-10, 4 * floor)
@@ -496,14 +524,21 @@ def main():
     res_max = float(norms[0])
     hbm_view = {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": BYTES_PER_CELL["f64"] * N * N}
+    tr = measured_traffic(tb, rows)
+    traffic = round(tr["read"] + tr["write"]) if tr else None
+    if tr:
+        hbm_view["traffic_read"] = round(tr["read"])
+        hbm_view["traffic_write"] = round(tr["write"])
+        hbm_view["traffic_over_algorithmic"] = round((tr["read"] + tr["write"]) / hbm_view["alg_bytes_per_launch"], 3)
+        hbm_view["actual_GBs"] = round((tr["read"] + tr["write"]) / per_launch_s / 1e9, 1)
     if tb == 1:
-        roofline = {"bound": "hbm", **hbm_view, "traffic": None}
+        roofline = {"bound": "hbm", **hbm_view, "traffic": traffic}
     else:
         # several sweeps per launch: HBM bytes per cell-update fall to 24/k and the
         # kernel is bound by vector ALU issue
         tflops = FLOPS_PER_CELL_SWEEP * N * N * tb / per_launch_s / 1e12
         roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(FP64_NOFMA_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(tflops / FP64_NOFMA_PEAK_TFLOPS, 4), "traffic": None,
+                    "unit": "TFLOP/s", "frac": round(tflops / FP64_NOFMA_PEAK_TFLOPS, 4), "traffic": traffic,
                     "alg_flops_per_launch": FLOPS_PER_CELL_SWEEP * N * N * tb, "hbm_view": hbm_view}
     roofline["kernel"] = f"relax_tb_kernel<double,2,{tb},*> ({rows or 'default'} rows per tile)"
 

@@ -176,7 +176,9 @@ typedef struct px_solve_opts {
     int norm;              /* 0: stop on max-norm, 1: on the L2 norm             */
     double rtol;           /* stop when ||r|| <= rtol * ||f|| (same norm)        */
     int64_t max_sweeps;    /* sweep budget (inner sweeps for MIXED modes)        */
-    int check_every;       /* sweeps between residual checks (PLAIN)             */
+    int check_every;       /* sweeps between residual checks (PLAIN); MIXED modes
+                              read the norms back every check_every / inner_sweeps
+                              outer steps (at least every step)                  */
     int inner_sweeps;      /* sweeps per inner solve (MIXED)                     */
     int tblock;            /* sweeps per launch, 0 = default                     */
     int bc;                /* px_bc                                              */
