@@ -321,27 +321,47 @@ typedef struct px_learned_opts {
     int64_t max_sweeps;   /* budget of relaxation sweeps                               */
     int smooth_sweeps;    /* plain sweeps after each correction (>= 1)                 */
     int tblock;           /* sweeps per launch, 0 = default                            */
-    int use_net;          /* 1: correction direction N(r / rms(r)); 0: direction r (the
-                             same loop without the network)                            */
+    int use_net;          /* correction directions: 0: r alone (the same loop without
+                             the network); 1: N(r / rms(r)) alone; 2: both, combined
+                             as px_correction_step mode 2                              */
 } px_learned_opts;
 
 typedef struct px_learned_stats {
     px_solve_stats base;  /* sweeps, outer_steps (= steps of the loop), norms, time    */
     int64_t corrections;  /* correction steps kept                                     */
     int64_t rejected;     /* correction steps undone by the judge                      */
-    int fell_back;        /* 1 when the solve finished with plain relaxation only      */
+    int fell_back;        /* 1 when a non-finite step switched corrections off         */
 } px_learned_stats;
 
 /*
+ * One correction step of the learned refinement (not in the paper): phi += a r + b d
+ * over the interior of phi ((n+2) x ld FP64, device, in place), with (a, b) chosen to
+ * minimise the energy norm <e, -L e> of the error e = L^-1 r after the step over the
+ * directions `mode` allows: 0: r alone (b = 0; d may be NULL); 1: d alone (a = 0);
+ * 2: both.  That is the Galerkin condition c M (a, b) = (<r,r>, <d,r>) with
+ * M = [<r,Sr> <r,Sd>; <r,Sd> <d,Sd>], c = 1/h^2, S the 5-point stencil with odd
+ * reflection (PX_BC_DIRICHLET0); a zero denominator gives a zero coefficient and a
+ * numerically singular M (|det| <= 1e-10 |<r,Sr><d,Sd>|) falls back to mode 0.
+ * r: device FP64 n x ld_r, the residual f - L phi; d: device n x ld_d, d_dtype PX_F64
+ * or PX_F32.  coef (device, 2 doubles, may be NULL) receives (a, b).  Dot products are
+ * FP64 in a fixed order.  phi must not overlap r or d (PX_EALIAS).
+ */
+int px_correction_step(void *phi, int n, int ld, const double *r, int ld_r, const void *d, int d_dtype, int ld_d,
+                       double h, int mode, double *coef, px_ctx *ctx, void *stream);
+
+/*
  * Solve L phi = f (FP64 phi and f, PX_BC_DIRICHLET0) by a refinement loop.  Each
- * step: r = f - L phi in FP64; a direction d (network output or r); the step
- * length a = <r, d> / <d, L d> that minimises the energy norm of the error along
- * d; phi += a d (FP64); then smooth_sweeps fused relaxation sweeps.  Plain
- * relaxation judges the step: if the residual L2 norm after it is not below the
- * one before, or not finite, the step is undone and the solve continues with plain
- * relaxation alone (the loop of px_solve PX_SOLVE_PLAIN with check_every =
- * smooth_sweeps).  Stopping rules and return codes as px_solve.  Waits on
- * `stream` every step.  net may be NULL when use_net is 0.  stats may be NULL.
+ * step: r = f - L phi in FP64; the correction step of px_correction_step with
+ * d = N(r / rms(r)) and mode = use_net (FP64 update); then smooth_sweeps fused
+ * relaxation sweeps.  Plain
+ * relaxation judges each step by its FP64 residual: if the L2 norm after the step
+ * (and its sweeps) is not below the one before, the step is undone and the next
+ * 1, 2, 4, ... (at most 64, doubling while steps keep failing, reset by a kept step)
+ * steps are plain relaxation; if it is not finite (a broken network) the step is
+ * undone and the solve continues with plain relaxation alone, which then equals the
+ * loop of px_solve PX_SOLVE_PLAIN with check_every = smooth_sweeps.  Stopping rules
+ * and return codes as px_solve.  Waits on `stream` every step.  net may be NULL when
+ * use_net is 0.  stats may be NULL.
  */
 int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double h, double lambda,
                      px_net *net, const px_learned_opts *opts, px_learned_stats *stats, px_ctx *ctx,

@@ -76,7 +76,7 @@ EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile
            "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched",
            "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
            "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
-           "px_net_make_pair", "px_solve_learned")
+           "px_net_make_pair", "px_correction_step", "px_solve_learned")
 
 _lib = None
 
@@ -119,11 +119,12 @@ def lib() -> ctypes.CDLL:
     L.px_net_adam.argtypes = [P, ctypes.c_float, P]
     L.px_net_activation.argtypes = [P, I, P, P]
     L.px_net_make_pair.argtypes = [P, I, I, I, P, P, P, P]
+    L.px_correction_step.argtypes = [P, I, I, P, I, P, I, I, D, I, P, P, P]
     L.px_solve_learned.argtypes = [P, I, I, P, I, D, D, P, ctypes.POINTER(_LearnedOpts),
                                    ctypes.POINTER(_LearnedStats), P, P]
     for nm in ("px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
                "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
-               "px_net_make_pair", "px_solve_learned",
+               "px_net_make_pair", "px_correction_step", "px_solve_learned",
                "px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
                "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
                "px_apply_stencil", "px_residual", "px_jacobi_update", "px_relax_fused", "px_solve"):
@@ -463,6 +464,20 @@ def make_pair(phi, n, x, t, ctx: Context, loss=LOSS_MSE, stream=None):
                                   _stream_handle(stream)))
 
 
+def correction_step(phi, n, r, d, h, ctx: Context, mode=2, coef=None, stream=None):
+    """phi += a r + b d with the energy-optimal (a, b) for mode (0: r, 1: d, 2: both);
+    r float64 (n, >= n), d float64/float32 (n, >= n) or None (mode 0); coef: float64
+    device tensor of 2 receiving (a, b), or None."""
+    ld = _ld(phi, n + 2, n + 2, "phi")
+    ldr = _ld(r, n, n, "r")
+    if d is None:
+        dp, ddt, ldd = ctypes.c_void_p(0), F64, 0
+    else:
+        dp, ddt, ldd = _ptr(d), dtype_code(d), _ld(d, n, n, "d")
+    _check(lib().px_correction_step(_ptr(phi), n, ld, _ptr(r), ldr, dp, ddt, ldd, float(h), int(mode),
+                                    _ptr(coef), ctx.handle, _stream_handle(stream)))
+
+
 @dataclass
 class LearnedStats(SolveStats):
     corrections: int = 0
@@ -470,15 +485,15 @@ class LearnedStats(SolveStats):
     fell_back: int = 0
 
 
-def solve_learned(phi, n, f, h, lam, ctx: Context, net: "Net | None" = None, use_net=True, rtol=1e-10,
+def solve_learned(phi, n, f, h, lam, ctx: Context, net: "Net | None" = None, use_net=1, rtol=1e-10,
                   norm=0, max_sweeps=10 ** 9, smooth_sweeps=16, tblock=0, stream=None,
                   raise_on_error=True) -> LearnedStats:
-    """Refinement loop with network (or residual) directions, energy-optimal steps, plain
-    smoothing sweeps and the plain-relaxation judge; float64 phi and f, in place."""
+    """Refinement loop with energy-optimal correction steps along r (use_net 0), the
+    network's direction (1) or both (2), plain smoothing sweeps and the plain-relaxation
+    judge; float64 phi and f, in place."""
     ld = _ld(phi, n + 2, n + 2, "phi")
     ldf = _ld(f, n, n, "f")
-    o = _LearnedOpts(int(norm), float(rtol), int(max_sweeps), int(smooth_sweeps), int(tblock),
-                     1 if use_net else 0)
+    o = _LearnedOpts(int(norm), float(rtol), int(max_sweeps), int(smooth_sweeps), int(tblock), int(use_net))
     s = _LearnedStats()
     st = lib().px_solve_learned(_ptr(phi), n, ld, _ptr(f), ldf, float(h), float(lam),
                                 net.handle if net is not None else ctypes.c_void_p(0), ctypes.byref(o),

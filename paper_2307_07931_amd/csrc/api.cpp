@@ -765,6 +765,37 @@ int px_net_make_pair(const double *phi, int n, int ld, int loss, float *x, float
     return PX_OK;
 }
 
+int px_correction_step(void *phi, int n, int ld, const double *r, int ld_r, const void *d, int d_dtype, int ld_d,
+                       double h, int mode, double *coef, px_ctx *ctx, void *stream)
+{
+    int st = check_n_ld(n, ld, F64);
+    if (st) return st;
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = check_ptr(phi, F64, "phi"))) return st;
+    if ((st = check_flat(r, n, ld_r, F64, "r"))) return st;
+    if (mode < 0 || mode > 2) return fail(PX_EINVAL, "mode must be 0, 1 or 2");
+    if (!d) {
+        if (mode != 0) return fail(PX_EINVAL, "d is NULL");
+        d = r;
+        d_dtype = F64;
+        ld_d = ld_r;
+    }
+    if (d_dtype != F64 && d_dtype != F32) return fail(PX_EINVAL, "d_dtype must be PX_F64 or PX_F32");
+    if ((st = check_flat(d, n, ld_d, d_dtype, "d"))) return st;
+    if ((st = check_pos(h, "h"))) return st;
+    const size_t gb = grid_bytes(n, ld, F64);
+    if (overlap(phi, gb, r, flat_bytes(n, ld_r, F64)) || overlap(phi, gb, d, flat_bytes(n, ld_d, d_dtype)))
+        return fail(PX_EALIAS, "phi overlaps r or d");
+    if ((st = set_device(ctx))) return st;
+    const size_t pb = sizeof(double) * 8 * (size_t)pair_num_blocks(n);
+    if ((st = ensure_mix(ctx, pb + 8 * sizeof(double)))) return st;
+    double *part = static_cast<double *>(ctx->mix);
+    PX_HIP(correction_launch(d_dtype, d, ld_d, r, ld_r, static_cast<double *>(phi), n, ld, 1.0 / (h * h), mode, part,
+                             part + pb / sizeof(double), coef, (hipStream_t)stream),
+           "correction step launch");
+    return PX_OK;
+}
+
 int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double h, double lambda, px_net *net,
                      const px_learned_opts *o, px_learned_stats *stats, px_ctx *ctx, void *stream)
 {
@@ -781,7 +812,7 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
     if (o->max_sweeps < 0) return fail(PX_EINVAL, "max_sweeps < 0");
     if (o->smooth_sweeps < 1) return fail(PX_EINVAL, "smooth_sweeps must be >= 1");
     if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
-    if (o->use_net != 0 && o->use_net != 1) return fail(PX_EINVAL, "use_net must be 0 or 1");
+    if (o->use_net < 0 || o->use_net > 2) return fail(PX_EINVAL, "use_net must be 0, 1 or 2");
     if (o->use_net && !net) return fail(PX_EINVAL, "use_net needs a network");
     if (o->use_net && net_device(net) != ctx->device)
         return fail(PX_EINVAL, "network on device %d, context on device %d", net_device(net), ctx->device);
@@ -795,7 +826,7 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
     const int ld_r = (n + 31) / 32 * 32, ld_y = (n + 63) / 64 * 64;
     const size_t o_r = up(gb), o_y = o_r + up(sizeof(double) * (size_t)n * ld_r);
     const size_t o_p = o_y + up(sizeof(float) * (size_t)n * ld_y);
-    const size_t o_d = o_p + up(sizeof(double) * 2 * (size_t)pair_num_blocks(n));
+    const size_t o_d = o_p + up(sizeof(double) * 8 * (size_t)pair_num_blocks(n));
     if ((st = ensure_mix(ctx, o_d + 256))) return st;
     char *mb = static_cast<char *>(ctx->mix);
     double *save = reinterpret_cast<double *>(mb);
@@ -850,6 +881,8 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
 
     if ((st = residual_into(ctx, F64, cur, n, ld, f, ld_f, h, DIRICHLET0, r, ld_r, ctx->norms_dev, s))) return st;
     if ((st = read_norms(nr))) return st;
+    bool r_fresh = true;  // r holds the residual of cur
+    int backoff = 0, skip = 0;
     const double r0 = measure(nr);
     for (;;) {
         const double m = measure(nr);
@@ -858,7 +891,10 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
         if (m > 1e8 * std::max(r0, fref)) { result = fail(PX_EDIVERGED, "residual grew from %g to %g", r0, m); break; }
         if (S.base.sweeps >= o->max_sweeps) { result = fail(PX_ENOTCONV, "max_sweeps reached (rel res %g)", m / fref); break; }
         const int todo = (int)std::min<int64_t>(o->smooth_sweeps, o->max_sweeps - S.base.sweeps);
-        if (correct) {
+        if (correct && skip == 0) {
+            if (!r_fresh &&
+                (st = residual_into(ctx, F64, cur, n, ld, f, ld_f, h, DIRICHLET0, r, ld_r, ctx->norms_dev, s)))
+                return st;
             PX_HIP(copy_grid_launch(F64, cur, save, n, ld, s), "copy kernel launch");
             const double rms = std::sqrt(nr[1] / ((double)n * (double)n));
             const void *d = r;
@@ -869,30 +905,44 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
                 ddt = F32;
                 ld_d = ld_y;
             }
-            PX_HIP(dots_launch(ddt, d, ld_d, r, ld_r, n, part, dots, s), "dots kernel launch");
-            PX_HIP(step_launch(ddt, d, ld_d, static_cast<double *>(cur), n, ld, c, dots, s), "step kernel launch");
+            PX_HIP(correction_launch(ddt, d, ld_d, r, ld_r, static_cast<double *>(cur), n, ld, c, o->use_net, part,
+                                     dots, nullptr, s),
+                   "correction step launch");
             if ((st = smooth(todo, false))) return st;
             if ((st = residual_into(ctx, F64, cur, n, ld, f, ld_f, h, DIRICHLET0, r, ld_r, ctx->norms_dev, s)))
                 return st;
             double nn[2];
             if ((st = read_norms(nn))) return st;
-            if (std::isfinite(nn[0]) && std::isfinite(nn[1]) && nn[1] < nr[1]) {
+            const bool finite = std::isfinite(nn[0]) && std::isfinite(nn[1]);
+            if (finite && nn[1] < nr[1]) {
                 S.corrections += 1;
                 S.base.sweeps += todo;
                 S.base.outer_steps += 1;
                 nr[0] = nn[0];
                 nr[1] = nn[1];
+                r_fresh = true;
+                backoff = 0;
             } else {
-                // the judge: undo the step and continue with plain relaxation only
+                // the judge: plain relaxation's residual did not drop -- undo the step and
+                // relax plainly for a back-off period (doubling while steps keep failing);
+                // a non-finite result means a broken network: plain relaxation from here on
                 PX_HIP(copy_grid_launch(F64, save, cur, n, ld, s), "copy kernel launch");
                 S.rejected += 1;
-                S.fell_back = 1;
-                correct = false;
+                r_fresh = false;
+                if (!finite) {
+                    S.fell_back = 1;
+                    correct = false;
+                } else {
+                    backoff = backoff ? std::min(2 * backoff, 64) : 1;
+                    skip = backoff;
+                }
             }
         } else {
             if ((st = smooth(todo, true))) return st;
             S.base.sweeps += todo;
             S.base.outer_steps += 1;
+            r_fresh = false;
+            if (skip > 0) skip -= 1;
             if ((st = read_norms(nr))) return st;
         }
     }

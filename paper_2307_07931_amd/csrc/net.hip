@@ -480,36 +480,88 @@ __global__ __launch_bounds__(BX) void pair_write_kernel(const double *__restrict
     t[(long long)i * n + j] = rt > 0.0 ? (float)(-in[(long long)i * ld + j] / rt) : 0.0f;
 }
 
-// Per-block partial sums {<r, d>, <d, S d>} over the n x n interior.
+// Per-block partial sums of the correction step over the n x n interior:
+// {<r, r>, <d, r>, <r, S r>, <r, S d>, <d, S d>} (S with odd reflection; S is symmetric,
+// so <d, S r> = <r, S d>).  part: 8 doubles per block.
 template <typename TD>
 __global__ __launch_bounds__(BX) void dots_kernel(const TD *__restrict__ d, int ld_d, const double *__restrict__ r,
-                                                  int ld_r, int n, double2 *__restrict__ part)
+                                                  int ld_r, int n, double *__restrict__ part)
 {
     __shared__ double sh[BX];
     const int i = blockIdx.y, j = blockIdx.x * BX + threadIdx.x;
-    double a = 0.0, b = 0.0;
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (j < n) {
-        const double dv = (double)d[(long long)i * ld_d + j];
-        a = r[(long long)i * ld_r + j] * dv;
-        b = dv * stencil_odd(d, ld_d, n, i, j);
+        const double rv = r[(long long)i * ld_r + j], dv = (double)d[(long long)i * ld_d + j];
+        const double sr = stencil_odd(r, ld_r, n, i, j), sd = stencil_odd(d, ld_d, n, i, j);
+        v[0] = rv * rv;
+        v[1] = dv * rv;
+        v[2] = rv * sr;
+        v[3] = rv * sd;
+        v[4] = dv * sd;
     }
-    const double ta = block_sum(a, sh);
-    __syncthreads();
-    const double tb = block_sum(b, sh);
-    if (threadIdx.x == 0) part[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(ta, tb);
+    double *dst = part + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * 8;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const double t = block_sum(v[q], sh);
+        if (threadIdx.x == 0) dst[q] = t;
+        __syncthreads();
+    }
 }
 
-// phi(i, j) += a d(i, j) over the interior, a = dots[0] / (c dots[1]), 0 if dots[1] == 0.
+// out[q] = sum over blocks (fixed order) of part[blk * 8 + q], q = 0..4.
+__global__ __launch_bounds__(BX) void sum5_partials_kernel(const double *__restrict__ part, int count,
+                                                           double *__restrict__ out)
+{
+    __shared__ double sh[BX];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < count; k += BX) s = s + part[(size_t)k * 8 + q];
+        const double t = block_sum(s, sh);
+        if (threadIdx.x == 0) out[q] = t;
+        __syncthreads();
+    }
+}
+
+// Coefficients (a, b) of phi += a r + b d that minimise the energy norm of the error
+// e (L e = r, L = c S) over the allowed directions: the Galerkin conditions
+// <v, L(a r + b d)> = <v, r> for v in the span, i.e. c M (a, b) = (<r,r>, <d,r>) with
+// M = [<r,Sr> <r,Sd>; <r,Sd> <d,Sd>].  mode 0: r only; 1: d only; 2: both (r only if
+// M is numerically singular).  A zero denominator gives a zero step.
+__device__ __forceinline__ void step_coefficients(const double *dots, double c, int mode, double &a, double &b)
+{
+    const double rr = dots[0], dr = dots[1], rsr = dots[2], rsd = dots[3], dsd = dots[4];
+    a = 0.0;
+    b = 0.0;
+    if (mode == 2) {
+        const double det = rsr * dsd - rsd * rsd;
+        if (fabs(det) > 1e-10 * fabs(rsr * dsd)) {
+            a = (rr * dsd - rsd * dr) / (c * det);
+            b = (rsr * dr - rsd * rr) / (c * det);
+            return;
+        }
+        mode = 0;
+    }
+    if (mode == 0) a = rsr != 0.0 ? rr / (c * rsr) : 0.0;
+    else b = dsd != 0.0 ? dr / (c * dsd) : 0.0;
+}
+
+// phi(i, j) += a r(i, j) + b d(i, j) over the interior; coef (if not NULL) gets (a, b).
 template <typename TD>
-__global__ __launch_bounds__(BX) void step_kernel(const TD *__restrict__ d, int ld_d, double *__restrict__ phi, int n,
-                                                  int ld, double c, const double *__restrict__ dots)
+__global__ __launch_bounds__(BX) void step_kernel(const TD *__restrict__ d, int ld_d, const double *__restrict__ r,
+                                                  int ld_r, double *__restrict__ phi, int n, int ld, double c,
+                                                  const double *__restrict__ dots, int mode, double *__restrict__ coef)
 {
     const int i = blockIdx.y, j = blockIdx.x * BX + threadIdx.x;
+    double a, b;
+    step_coefficients(dots, c, mode, a, b);
+    if (coef && i == 0 && j == 0) {
+        coef[0] = a;
+        coef[1] = b;
+    }
     if (j >= n) return;
-    const double den = c * dots[1];
-    const double a = den != 0.0 ? dots[0] / den : 0.0;
     double *p = phi + (long long)(i + 1) * ld + (j + 1);
-    *p = *p + a * (double)d[(long long)i * ld_d + j];
+    *p = (*p + a * r[(long long)i * ld_r + j]) + b * (double)d[(long long)i * ld_d + j];
 }
 
 inline unsigned blocks_for(long long n) { return (unsigned)((n + BX - 1) / BX); }
@@ -689,29 +741,21 @@ hipError_t pair_launch(const double *phi, int n, int ld, int loss, float *x, flo
     return hipGetLastError();
 }
 
-hipError_t dots_launch(int ddtype, const void *d, int ld_d, const double *r, int ld_r, int n, double *part,
-                       double *dots, hipStream_t s)
+hipError_t correction_launch(int ddtype, const void *d, int ld_d, const double *r, int ld_r, double *phi, int n,
+                             int ld, double c, int mode, double *part, double *dots, double *coef, hipStream_t s)
 {
     const dim3 grid(blocks_for(n), n);
     if (ddtype == F64)
-        hipLaunchKernelGGL(dots_kernel<double>, grid, dim3(BX), 0, s, (const double *)d, ld_d, r, ld_r, n,
-                           (double2 *)part);
+        hipLaunchKernelGGL(dots_kernel<double>, grid, dim3(BX), 0, s, (const double *)d, ld_d, r, ld_r, n, part);
     else
-        hipLaunchKernelGGL(dots_kernel<float>, grid, dim3(BX), 0, s, (const float *)d, ld_d, r, ld_r, n,
-                           (double2 *)part);
-    hipLaunchKernelGGL(sum2_partials_kernel, dim3(1), dim3(BX), 0, s, (const double2 *)part, pair_num_blocks(n),
-                       dots);
-    return hipGetLastError();
-}
-
-hipError_t step_launch(int ddtype, const void *d, int ld_d, double *phi, int n, int ld, double c, const double *dots,
-                       hipStream_t s)
-{
-    const dim3 grid(blocks_for(n), n);
+        hipLaunchKernelGGL(dots_kernel<float>, grid, dim3(BX), 0, s, (const float *)d, ld_d, r, ld_r, n, part);
+    hipLaunchKernelGGL(sum5_partials_kernel, dim3(1), dim3(BX), 0, s, (const double *)part, pair_num_blocks(n), dots);
     if (ddtype == F64)
-        hipLaunchKernelGGL(step_kernel<double>, grid, dim3(BX), 0, s, (const double *)d, ld_d, phi, n, ld, c, dots);
+        hipLaunchKernelGGL(step_kernel<double>, grid, dim3(BX), 0, s, (const double *)d, ld_d, r, ld_r, phi, n, ld, c,
+                           (const double *)dots, mode, coef);
     else
-        hipLaunchKernelGGL(step_kernel<float>, grid, dim3(BX), 0, s, (const float *)d, ld_d, phi, n, ld, c, dots);
+        hipLaunchKernelGGL(step_kernel<float>, grid, dim3(BX), 0, s, (const float *)d, ld_d, r, ld_r, phi, n, ld, c,
+                           (const double *)dots, mode, coef);
     return hipGetLastError();
 }
 

@@ -144,12 +144,11 @@ int net_device(const px_net *net);
 int pair_num_blocks(int n);
 hipError_t pair_launch(const double *phi, int n, int ld, int loss, float *x, float *t, double *part,
                        double *sums, hipStream_t s);
-// Step of the learned refinement: dots = {<r, d>, <d, S d>} (S with odd reflection, d
-// compact n x ld_d, FP32 or FP64), then phi += a d with a = dots[0] / (c dots[1]) (0 when
-// dots[1] == 0).  part: >= pair_num_blocks(n) double2 slots.
-hipError_t dots_launch(int ddtype, const void *d, int ld_d, const double *r, int ld_r, int n, double *part,
-                       double *dots, hipStream_t s);
-hipError_t step_launch(int ddtype, const void *d, int ld_d, double *phi, int n, int ld, double c,
-                       const double *dots, hipStream_t s);
+// Correction step of the learned refinement: the five sums {<r,r>, <d,r>, <r,Sr>, <r,Sd>,
+// <d,Sd>} (S with odd reflection; d compact n x ld_d, FP32 or FP64) into dots (5 doubles),
+// then phi += a r + b d with the energy-optimal (a, b) for `mode` (0: r, 1: d, 2: both);
+// coef (may be NULL) receives (a, b).  part: >= 8 * pair_num_blocks(n) doubles.
+hipError_t correction_launch(int ddtype, const void *d, int ld_d, const double *r, int ld_r, double *phi, int n,
+                             int ld, double c, int mode, double *part, double *dots, double *coef, hipStream_t s);
 
 }  // namespace px

@@ -253,7 +253,33 @@ def test_solve_learned_validation(ctx):
     assert run(max_sweeps=-1) == px.EINVAL
     assert run(smooth=0) == px.EINVAL
     assert run(tblock=9) == px.EINVAL
-    assert run(use_net=2) == px.EINVAL
+    assert run(use_net=3) == px.EINVAL
+    assert run(use_net=-1) == px.EINVAL
     assert run(use_net=1) == px.EINVAL  # no network
     assert "network" in px.last_error()
     assert run(f=FAKE + 8) == px.EALIAS
+
+
+def test_correction_step_validation(ctx):
+    L = px.lib()
+    P = ctypes.c_void_p
+
+    def run(**kw):
+        return L.px_correction_step(P(kw.get("phi", FAKE)), kw.get("n", 64), kw.get("ld", 66), P(kw.get("r", FAKE2)),
+                                    kw.get("ld_r", 64), P(kw.get("d", FAKE2 * 2)), kw.get("ddt", px.F32),
+                                    kw.get("ld_d", 64), kw.get("h", 1 / 64), kw.get("mode", 2), None,
+                                    kw.get("ctx", ctx), None)
+
+    assert run(ctx=None) == px.EINVAL
+    assert run(n=0) == px.EINVAL
+    assert run(ld=65) == px.EINVAL
+    assert run(phi=0) == px.EINVAL
+    assert run(r=0) == px.EINVAL
+    assert run(ld_r=63) == px.EINVAL
+    assert run(mode=3) == px.EINVAL
+    assert run(d=0) == px.EINVAL  # mode 2 needs d
+    assert run(ddt=px.BF16) == px.EINVAL
+    assert run(ld_d=10) == px.EINVAL
+    assert run(h=0.0) == px.EINVAL
+    assert run(r=FAKE + 64) == px.EALIAS
+    assert run(d=FAKE + 64) == px.EALIAS
