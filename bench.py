@@ -390,6 +390,10 @@ def batched_workload(px, ctx, count=512, solve_count=64):
         items.append((phi, f, n, h, OMEGA * h * h / 4.0))
         cells += n * n
     sweeps = 64
+    t0 = time.perf_counter()
+    kb = px.autotune_batched(items, ctx)  # relaxes the problems in place; contents do not matter here
+    out["autotune"] = {"k": kb, "seconds": round(time.perf_counter() - t0, 2)}
+    log(f"  batched autotune: k={kb} ({out['autotune']['seconds']} s)")
     tb = time_region(lambda: px.relax_batched(items, sweeps, ctx, resmode=px.RES_NONE), reps=3, warmup=1)
     scratch = {}
 
@@ -416,6 +420,13 @@ def batched_workload(px, ctx, count=512, solve_count=64):
             f[:, :n] = torch.from_numpy(W.uniform_rhs(n, W.SEED_BATCH_BASE + i)).cuda()
             its.append((phi, f, n, h, OMEGA * h * h / 4.0))
         return its
+    # tune the FP32 inner sweeps on scratch FP32 problems of the same sizes
+    tune = []
+    for i, n in small:
+        h = 1.0 / n
+        tune.append((px.alloc_grid(n, torch.float32), px.alloc_rhs(n, torch.float32), n, h, OMEGA * h * h / 4.0))
+    k_solve = px.autotune_batched(tune, ctx)
+    del tune
     its = build()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -428,7 +439,7 @@ def batched_workload(px, ctx, count=512, solve_count=64):
            for phi, f, n, h, lam in its2]
     t_seq = time.perf_counter() - t0
     same = all(torch.equal(a[0], b[0]) for a, b in zip(its, its2))
-    out["solve"] = {"problems": len(small), "sizes": sorted({n for _, n in small}), "rtol": 1e-8,
+    out["solve"] = {"problems": len(small), "sizes": sorted({n for _, n in small}), "rtol": 1e-8, "k_tuned": k_solve,
                     "status": status, "batched_s": t_batch, "sequential_s": t_seq, "speedup": t_seq / t_batch,
                     "max_rel_res": max(s.rel_res_max for s in stats), "results_identical_to_sequential": same,
                     "total_sweeps": int(sum(s.sweeps for s in stats))}

@@ -230,6 +230,20 @@ int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps,
                      int resmode, double *norms, px_ctx *ctx, void *stream);
 
 /*
+ * Autotuner for batches: the tile rows of each problem size (the problems of that size
+ * relaxed alone with the persistent kernel, 8 sweeps per launch, every candidate height),
+ * then the sweeps per launch k in 1..8 for the whole batch.  Remembered in ctx for
+ * dtype: px_relax_batched (dtype) and px_solve_batched (inner sweeps of that dtype:
+ * PX_F32 for PX_SOLVE_MIXED_F32, PX_BF16 for PX_SOLVE_MIXED_BF16) use them when tblock
+ * is 0 (px_ctx_set_tile_rows still overrides the rows).  Any dtype's results are
+ * identical with or without tuning.  The problems are relaxed IN PLACE while timing
+ * (their phi is overwritten): pass scratch problems of the same sizes, or
+ * re-initialise them afterwards.  Waits on `stream`.  best_k may be NULL.
+ */
+int px_autotune_batched(const px_problem *probs, int nprob, int dtype, int bc, px_ctx *ctx, void *stream,
+                        int *best_k);
+
+/*
  * Solve every problem of the batch to its tolerance with FP64 iterative
  * refinement around low-precision inner sweeps (opts->mode PX_SOLVE_MIXED_F32
  * or PX_SOLVE_MIXED_BF16; phi and f are FP64; the arithmetic is that of

@@ -74,7 +74,7 @@ class _Problem(ctypes.Structure):
 EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile_rows",
            "px_autotune", "px_last_error", "px_version", "px_apply_stencil", "px_residual",
            "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched",
-           "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
+           "px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
            "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
            "px_net_make_pair", "px_correction_step", "px_solve_learned")
 
@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
     L.px_autotune.argtypes = [P, P, I, I, I, P, I, I, P, P, ctypes.POINTER(I), ctypes.POINTER(I),
                               ctypes.POINTER(D)]
     L.px_relax_batched.argtypes = [ctypes.POINTER(_Problem), I, I, I, I, I, I, P, P, P]
+    L.px_autotune_batched.argtypes = [ctypes.POINTER(_Problem), I, I, I, P, P, ctypes.POINTER(I)]
     L.px_solve_batched.argtypes = [ctypes.POINTER(_Problem), I, ctypes.POINTER(_SolveOpts),
                                    ctypes.POINTER(_SolveStats), P, P]
     F = ctypes.POINTER(ctypes.c_float)
@@ -122,7 +123,7 @@ def lib() -> ctypes.CDLL:
     L.px_correction_step.argtypes = [P, I, I, P, I, P, I, I, D, I, P, P, P]
     L.px_solve_learned.argtypes = [P, I, I, P, I, D, D, P, ctypes.POINTER(_LearnedOpts),
                                    ctypes.POINTER(_LearnedStats), P, P]
-    for nm in ("px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
+    for nm in ("px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
                "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
                "px_net_make_pair", "px_correction_step", "px_solve_learned",
                "px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
@@ -345,6 +346,16 @@ def relax_batched(items, nsweeps, ctx: Context, tblock=0, bc=BC_DIRICHLET0, resm
     arr, dt = _problems(items)
     _check(lib().px_relax_batched(arr, len(items), _DTYPE_CODE[dt], int(nsweeps), int(tblock), int(bc),
                                   int(resmode), _ptr(norms), ctx.handle, _stream_handle(stream)))
+
+
+def autotune_batched(items, ctx: Context, bc=BC_DIRICHLET0, stream=None) -> int:
+    """Tunes tile rows per problem size and sweeps per launch for batches of these
+    problems' dtype (relaxes them in place while timing); returns the chosen k."""
+    arr, dt = _problems(items)
+    k = ctypes.c_int()
+    _check(lib().px_autotune_batched(arr, len(items), _DTYPE_CODE[dt], int(bc), ctx.handle,
+                                     _stream_handle(stream), ctypes.byref(k)))
+    return k.value
 
 
 def solve_batched(items, ctx: Context, mode=SOLVE_MIXED_F32, rtol=1e-8, norm=0, max_sweeps=10 ** 9,

@@ -693,8 +693,24 @@ int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps,
     if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
     if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
     char err[256] = "";
-    st = batch_relax(*ctx->batch, dtype, bp.data(), nprob, nsweeps, tblock ? tblock : 8, bc, resmode, norms,
-                     ctx->tile_rows, (hipStream_t)stream, err, sizeof err);
+    const int tk = ctx->batch->tuned_k[dtype];
+    st = batch_relax(*ctx->batch, dtype, bp.data(), nprob, nsweeps, tblock ? tblock : (tk ? tk : 8), bc, resmode,
+                     norms, ctx->tile_rows, (hipStream_t)stream, err, sizeof err);
+    return st ? fail(st, "%s", err) : PX_OK;
+}
+
+int px_autotune_batched(const px_problem *probs, int nprob, int dtype, int bc, px_ctx *ctx, void *stream, int *best_k)
+{
+    std::vector<BatchProblem> bp;
+    int st = check_batch(probs, nprob, dtype, bp);
+    if (st) return st;
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = set_device(ctx))) return st;
+    if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+    if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
+    char err[256] = "";
+    st = batch_autotune(*ctx->batch, dtype, bp.data(), nprob, bc, (hipStream_t)stream, best_k, err, sizeof err);
     return st ? fail(st, "%s", err) : PX_OK;
 }
 
@@ -715,13 +731,14 @@ int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *o,
     if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
     if (!valid_bc(o->bc)) return fail(PX_EINVAL, "unknown bc %d", o->bc);
     const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : 32;
-    const int k = std::min(o->tblock ? o->tblock : 8, inner);
     if ((st = set_device(ctx))) return st;
     if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
     if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
     std::vector<BatchStat> bs(nprob);
     char err[256] = "";
     const int lowp = o->mode == PX_SOLVE_MIXED_F32 ? F32 : BF16;
+    const int tk = ctx->batch->tuned_k[lowp];
+    const int k = std::min(o->tblock ? o->tblock : (tk ? tk : 8), inner);
     st = batch_solve(*ctx->batch, lowp, bp.data(), nprob, o->bc, o->rtol, o->norm, o->max_sweeps, inner, k, 8,
                      bs.data(), (hipStream_t)stream, err, sizeof err);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

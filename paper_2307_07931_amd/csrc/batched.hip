@@ -296,12 +296,15 @@ KArgs make_kargs(int dtype, const void *in, void *out, const void *f, int n, int
     return a;
 }
 
-int rows_for(int dtype, int n, int k, int forced)
-{
-    return forced > 0 ? forced : relax_default_rows(dtype, n, k);
-}
-
 }  // namespace
+
+int BatchWork::rows_for(int dtype, int n, int k, int forced) const
+{
+    if (forced > 0) return forced;
+    for (const auto &e : tuned_rows[dtype])
+        if (e.first == n) return e.second;
+    return relax_default_rows(dtype, n, k);
+}
 
 // ---------------------------------------------------------- scratch memory
 
@@ -358,7 +361,7 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
         for (int dir = 0; dir < 2; ++dir) sh.a[dir].resize(nprob);
         for (int p = 0; p < nprob; ++p) {
             const BatchProblem &q = probs[p];
-            const int rows = rows_for(dtype, q.n, kk, forced_rows);
+            const int rows = w.rows_for(dtype, q.n, kk, forced_rows);
             char *tmp = nullptr;  // filled after allocation
             sh.a[0][p] = make_kargs(dtype, q.phi, tmp, q.f, q.n, q.ld, q.ld_f, q.h, q.lambda, bc, kk, rm, rows);
             sh.a[1][p] = make_kargs(dtype, tmp, q.phi, q.f, q.n, q.ld, q.ld_f, q.h, q.lambda, bc, kk, rm, rows);
@@ -435,6 +438,90 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
         snprintf(err, errlen, "batched relaxation: %s", hipGetErrorString(e));
         return PX_EHIP;
     }
+    return PX_OK;
+}
+
+// --------------------------------------------------------------- autotuner
+
+// Tile rows per problem size: each size class relaxed alone (8 sweeps, one persistent
+// launch) for every candidate height, fastest of three timed runs after a warm-up.  Then
+// sweeps per launch for the whole batch: 24 sweeps at k = 1..8 with the tuned rows.
+int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int bc, hipStream_t s,
+                   int *best_k, char *err, size_t errlen)
+{
+    static const int ROWS[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128};
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        snprintf(err, errlen, "hipEventCreate failed");
+        return PX_EHIP;
+    }
+    int st = PX_OK;
+    // time `reps` runs of fn after one warm-up run; returns the fastest in ms (< 0 on error)
+    auto fastest = [&](auto &&fn, int reps) -> float {
+        if ((st = fn())) return -1.f;
+        float best = -1.f;
+        for (int r = 0; r < reps; ++r) {
+            if (hipEventRecord(e0, s) != hipSuccess) { st = PX_EHIP; return -1.f; }
+            if ((st = fn())) return -1.f;
+            float ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = PX_EHIP;
+                return -1.f;
+            }
+            if (best < 0.f || ms < best) best = ms;
+        }
+        return best;
+    };
+    w.tuned_rows[dtype].clear();
+    w.tuned_k[dtype] = 0;
+    std::vector<int> sizes;
+    for (int p = 0; p < nprob; ++p)
+        if (std::find(sizes.begin(), sizes.end(), probs[p].n) == sizes.end()) sizes.push_back(probs[p].n);
+    for (int n : sizes) {
+        std::vector<BatchProblem> cls;
+        for (int p = 0; p < nprob; ++p)
+            if (probs[p].n == n) cls.push_back(probs[p]);
+        int br = 0;
+        float bt = -1.f;
+        for (int rows : ROWS) {
+            if (rows > std::max(8, n + 2)) break;
+            const float ms = fastest([&] {
+                return batch_relax(w, dtype, cls.data(), (int)cls.size(), 8, 8, bc, RES_NONE, nullptr, rows, s, err,
+                                   errlen);
+            }, 3);
+            if (st) break;
+            if (bt < 0.f || ms < bt) {
+                bt = ms;
+                br = rows;
+            }
+        }
+        if (st) break;
+        w.tuned_rows[dtype].push_back({n, br});
+    }
+    int bk = 8;
+    if (!st) {
+        float bt = -1.f;
+        for (int k = 1; k <= 8 && !st; ++k) {
+            const float ms = fastest([&] {
+                return batch_relax(w, dtype, probs, nprob, 24, k, bc, RES_NONE, nullptr, 0, s, err, errlen);
+            }, 2);
+            if (st) break;
+            if (bt < 0.f || ms < bt) {
+                bt = ms;
+                bk = k;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) {
+        w.tuned_rows[dtype].clear();
+        if (!err[0]) snprintf(err, errlen, "batched autotune: HIP event failure");
+        return st;
+    }
+    w.tuned_k[dtype] = bk;
+    if (best_k) *best_k = bk;
     return PX_OK;
 }
 
@@ -547,7 +634,7 @@ int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, in
         r.bc = bc;
         r.c = 1.0 / (q.h * q.h);
         for (auto &sh : shapes) {
-            const int rows = rows_for(lowp, q.n, sh.k, 0);
+            const int rows = w.rows_for(lowp, q.n, sh.k, 0);
             sh.a[0][p] = make_kargs(lowp, base + da[p], base + db[p], base + rl[p], q.n, ldl[p], ldl[p], q.h,
                                     q.lambda, bc, sh.k, RES_NONE, rows);
             sh.a[1][p] = make_kargs(lowp, base + db[p], base + da[p], base + rl[p], q.n, ldl[p], ldl[p], q.h,

@@ -75,35 +75,55 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
     }
 }
 
+// Tiles of the thin layers: a block of BX threads owns 4 rows x 64 pixels, one pixel per
+// thread; the input patch (1-pixel halo) and the layer's weights are staged in LDS.
+constexpr int LT_ROWS = 4, LT_PX = 64;
+static_assert(LT_ROWS * LT_PX == BX, "one pixel per thread");
+
 // Layer 1: x (rows of ldx, FP64 or FP32) times `scale`, rounded to FP32 and then to
-// BF16, -> 32 channels, ReLU.
+// BF16, -> 32 channels, ReLU.  FP32 accumulation (fused multiply-add allowed).
 template <typename TX>
 __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, int ldx, double scale,
                                                     const bf16 *__restrict__ w1, bf16 *__restrict__ a1, int B,
                                                     int H, int W)
 {
-    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
-    if (p >= (long long)B * H * W) return;
-    const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+#pragma clang fp contract(fast)
+    __shared__ float sw[NW1];
+    __shared__ float sx[(LT_ROWS + 2) * (LT_PX + 2)];
+    const int tiles_w = (W + LT_PX - 1) / LT_PX, tiles_h = (H + LT_ROWS - 1) / LT_ROWS;
+    const int tw = (int)(blockIdx.x % tiles_w), th = (int)((blockIdx.x / tiles_w) % tiles_h);
+    const int b = (int)(blockIdx.x / ((unsigned)tiles_w * tiles_h));
+    const int i0 = th * LT_ROWS, j0 = tw * LT_PX;
+    for (int q = threadIdx.x; q < NW1; q += BX) sw[q] = bfv(w1[q]);
+    for (int q = threadIdx.x; q < (LT_ROWS + 2) * (LT_PX + 2); q += BX) {
+        const int pr = q / (LT_PX + 2), pc = q % (LT_PX + 2);
+        const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
+        float v = 0.0f;
+        if (ii >= 0 && ii < H && jj >= 0 && jj < W)
+            v = bf16_to_f32(f32_to_bf16_rne((float)((double)x[((long long)b * H + ii) * ldx + jj] * scale)));
+        sx[q] = v;
+    }
+    __syncthreads();
+    const int r = threadIdx.x / LT_PX, c = threadIdx.x % LT_PX;
+    const int i = i0 + r, j = j0 + c;
+    if (i >= H || j >= W) return;
     float xv[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
-        const bool ok = ii >= 0 && ii < H && jj >= 0 && jj < W;
-        const float v = ok ? (float)((double)x[((long long)b * H + ii) * ldx + jj] * scale) : 0.0f;
-        xv[t] = bf16_to_f32(f32_to_bf16_rne(v));
+    for (int t = 0; t < 9; ++t) xv[t] = sx[(r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))];
+    unsigned pk[C / 2];
+#pragma unroll
+    for (int co = 0; co < C; co += 2) {
+        float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            acc0 += sw[co * 9 + t] * xv[t];
+            acc1 += sw[(co + 1) * 9 + t] * xv[t];
+        }
+        pk[co / 2] = (unsigned)f32_to_bf16_rne(relu(acc0)) | ((unsigned)f32_to_bf16_rne(relu(acc1)) << 16);
     }
-    bf16 out[C];
+    uint4 *dst = reinterpret_cast<uint4 *>(a1 + (((long long)b * H + i) * W + j) * C);
 #pragma unroll
-    for (int co = 0; co < C; ++co) {
-        float acc = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) acc += bfv(w1[co * 9 + t]) * xv[t];
-        out[co] = tobf(relu(acc));
-    }
-    uint4 *dst = reinterpret_cast<uint4 *>(a1 + p * C);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(out)[q];
+    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
 }
 
 // 32 -> 32 convolution on the matrix cores, as an implicit GEMM per output tile.
@@ -125,6 +145,28 @@ __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, in
 constexpr int TROWS = 4, TPX = 64, PSTR = 40;
 constexpr int PROWS = TROWS + 2, PCOLS = TPX + 2;
 
+constexpr int PCHUNKS = PROWS * PCOLS * 4;            // 16-byte chunks of one patch
+constexpr int PPER = (PCHUNKS + BX - 1) / BX;         // chunks per thread
+
+// Issue the global loads of one tile's patch into registers (zeros outside the image).
+__device__ __forceinline__ void patch_load(const bf16 *__restrict__ in, int tile, int tiles_w, int tiles_h, int H,
+                                           int W, uint4 (&reg)[PPER])
+{
+    const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
+    const int i0 = th * TROWS, j0 = tw * TPX;
+#pragma unroll
+    for (int u = 0; u < PPER; ++u) {
+        const int q = (int)threadIdx.x + u * BX;
+        reg[u] = make_uint4(0, 0, 0, 0);
+        if (q < PCHUNKS) {
+            const int ch = q & 3, pc = (q >> 2) % PCOLS, pr = (q >> 2) / PCOLS;
+            const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
+            if (ii >= 0 && ii < H && jj >= 0 && jj < W)
+                reg[u] = *reinterpret_cast<const uint4 *>(in + (((long long)b * H + ii) * W + jj) * C + ch * 8);
+        }
+    }
+}
+
 template <bool MIRROR>
 __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wl,
                                                     bf16 *__restrict__ out, const bf16 *__restrict__ mask, int B,
@@ -138,22 +180,25 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
         *reinterpret_cast<uint4 *>(sw + row * PSTR + ch * 8) = *reinterpret_cast<const uint4 *>(wl + row * C + ch * 8);
     }
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
-    const long long ntiles = (long long)B * tiles_h * tiles_w;
+    const int ntiles = B * tiles_h * tiles_w;  // < 2^31: at most 2^31 pixels
     const int n = lane & 31, kg = lane >> 5;
-    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int tw = (int)(tile % tiles_w), th = (int)((tile / tiles_w) % tiles_h);
-        const int b = (int)(tile / ((long long)tiles_w * tiles_h));
+    uint4 reg[PPER];
+    if ((int)blockIdx.x < ntiles) patch_load(in, blockIdx.x, tiles_w, tiles_h, H, W, reg);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
         const int i0 = th * TROWS, j0 = tw * TPX;
         __syncthreads();  // the previous tile's LDS reads are done (first pass: weights stored)
-        for (int q = tid; q < PROWS * PCOLS * 4; q += BX) {
-            const int ch = q & 3, pc = (q >> 2) % PCOLS, pr = (q >> 2) / PCOLS;
-            const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (ii >= 0 && ii < H && jj >= 0 && jj < W)
-                v = *reinterpret_cast<const uint4 *>(in + (((long long)b * H + ii) * W + jj) * C + ch * 8);
-            *reinterpret_cast<uint4 *>(sp + (pr * PCOLS + pc) * PSTR + ch * 8) = v;
+#pragma unroll
+        for (int u = 0; u < PPER; ++u) {
+            const int q = tid + u * BX;
+            if (q < PCHUNKS) {
+                const int ch = q & 3, pix = q >> 2;
+                *reinterpret_cast<uint4 *>(sp + pix * PSTR + ch * 8) = reg[u];
+            }
         }
         __syncthreads();
+        // the next tile's patch loads fly while this tile's matrix products run
+        if (tile + (int)gridDim.x < ntiles) patch_load(in, tile + gridDim.x, tiles_w, tiles_h, H, W, reg);
         f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
@@ -198,21 +243,46 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
     }
 }
 
-// Layer 4: 32 channels -> 1, output FP32 into rows of ldy.
+// Layer 4: 32 channels -> 1, output FP32 into rows of ldy.  The a3 patch (6 x 66 pixels,
+// rows padded to PSTR elements) and the weights are staged in LDS; each thread reads its
+// 9 neighbours' 32 channels as 16-byte LDS loads.
 __global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const bf16 *__restrict__ w4,
                                                     float *__restrict__ y, int ldy, int B, int H, int W)
 {
-    const long long p = (long long)blockIdx.x * BX + threadIdx.x;
-    if (p >= (long long)B * H * W) return;
-    const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
+#pragma clang fp contract(fast)
+    __shared__ float sw[NW4];
+    __shared__ __align__(16) bf16 sp[(LT_ROWS + 2) * (LT_PX + 2) * PSTR];
+    const int tiles_w = (W + LT_PX - 1) / LT_PX, tiles_h = (H + LT_ROWS - 1) / LT_ROWS;
+    const int tw = (int)(blockIdx.x % tiles_w), th = (int)((blockIdx.x / tiles_w) % tiles_h);
+    const int b = (int)(blockIdx.x / ((unsigned)tiles_w * tiles_h));
+    const int i0 = th * LT_ROWS, j0 = tw * LT_PX;
+    for (int q = threadIdx.x; q < NW4; q += BX) sw[q] = bfv(w4[q]);
+    for (int q = threadIdx.x; q < (LT_ROWS + 2) * (LT_PX + 2) * 4; q += BX) {
+        const int ch = q & 3, pc = (q >> 2) % (LT_PX + 2), pr = (q >> 2) / (LT_PX + 2);
+        const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (ii >= 0 && ii < H && jj >= 0 && jj < W)
+            v = *reinterpret_cast<const uint4 *>(a3 + (((long long)b * H + ii) * W + jj) * C + ch * 8);
+        *reinterpret_cast<uint4 *>(sp + (pr * (LT_PX + 2) + pc) * PSTR + ch * 8) = v;
+    }
+    __syncthreads();
+    const int r = threadIdx.x / LT_PX, c = threadIdx.x % LT_PX;
+    const int i = i0 + r, j = j0 + c;
+    if (i >= H || j >= W) return;
     float acc = 0.0f;
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
-        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
-        const bf16 *a = a3 + (((long long)b * H + ii) * W + jj) * C;
+        const bf16 *px = sp + ((r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))) * PSTR;
 #pragma unroll
-        for (int ci = 0; ci < C; ++ci) acc += bfv(w4[ci * 9 + t]) * bfv(a[ci]);
+        for (int c8 = 0; c8 < 4; ++c8) {
+            const uint4 u = *reinterpret_cast<const uint4 *>(px + c8 * 8);
+            const unsigned wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc += sw[(c8 * 8 + 2 * e) * 9 + t] * __uint_as_float(wd[e] << 16);
+                acc += sw[(c8 * 8 + 2 * e + 1) * 9 + t] * __uint_as_float(wd[e] & 0xffff0000u);
+            }
+        }
     }
     y[((long long)b * H + i) * ldy + j] = acc;
 }
@@ -654,6 +724,11 @@ unsigned conv_blocks(int B, int H, int W)
     return (unsigned)std::min<long long>(tiles, 2048);  // 8 blocks per CU; blocks loop over tiles
 }
 
+unsigned thin_blocks(int B, int H, int W)
+{
+    return (unsigned)((long long)B * ((H + LT_ROWS - 1) / LT_ROWS) * ((W + LT_PX - 1) / LT_PX));
+}
+
 // Forward pass: y (rows of ldy) = N(x * scale); x rows of ldx, FP64 or FP32.
 hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scale, float *y, int ldy, int B, int H,
                        int W, hipStream_t st)
@@ -661,17 +736,18 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
     const long long N = (long long)B * H * W;
     hipError_t e = net_workspace(s, N);
     if (e != hipSuccess) return e;
+    const unsigned lt = thin_blocks(B, H, W);
     if (xdt == F64)
-        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(blocks_for(N)), dim3(BX), 0, st, (const double *)x, ldx,
-                           scale, s.nw.w1, s.a1, B, H, W);
+        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(lt), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1,
+                           s.a1, B, H, W);
     else
-        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(blocks_for(N)), dim3(BX), 0, st, (const float *)x, ldx, scale,
-                           s.nw.w1, s.a1, B, H, W);
+        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(lt), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1,
+                           s.a1, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a1, s.nw.w2f, s.a2,
                        (const bf16 *)nullptr, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
                        (const bf16 *)nullptr, B, H, W);
-    hipLaunchKernelGGL(l4_fwd_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(lt), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
     s.last_pixels = N;
     return hipGetLastError();
 }

@@ -7,6 +7,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+#include <vector>
+
 struct px_net;
 
 namespace px {
@@ -122,11 +125,19 @@ struct BatchWork {
     size_t bytes = 0;
     void *stream = nullptr;
     void *graph_exec = nullptr;
+    // autotuned per element type: sweeps per launch (0 = not tuned) and tile rows per
+    // problem size n (sizes not listed use the built-in heuristic)
+    int tuned_k[3] = {0, 0, 0};
+    std::vector<std::pair<int, int>> tuned_rows[3];
+    int rows_for(int dtype, int n, int k, int forced) const;
     ~BatchWork();
     hipError_t ensure(size_t need);
 };
 int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int nsweeps, int k, int bc,
                 int resmode, double *norms, int forced_rows, hipStream_t s, char *err, size_t errlen);
+// Autotuner of batched relaxation (see px_autotune_batched); relaxes the problems in place.
+int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int bc, hipStream_t s,
+                   int *best_k, char *err, size_t errlen);
 int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, int bc, double rtol,
                 int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, BatchStat *stats,
                 hipStream_t user_stream, char *err, size_t errlen);

@@ -199,6 +199,12 @@ def test_batched_validation(ctx):
     o = px._SolveOpts(px.SOLVE_MIXED_F32, 3, 1e-8, 100, 0, 8, 0, 0)
     assert L.px_solve_batched(probs, 2, ctypes.byref(o), st, ctx, None) == px.EINVAL
     assert L.px_solve_batched(probs, 2, None, st, ctx, None) == px.EINVAL
+    k = ctypes.c_int()
+    assert L.px_autotune_batched(probs, 0, px.F64, 0, ctx, None, ctypes.byref(k)) == px.EINVAL
+    assert L.px_autotune_batched(probs, 2, 7, 0, ctx, None, ctypes.byref(k)) == px.EINVAL
+    assert L.px_autotune_batched(probs, 2, px.F64, 5, ctx, None, ctypes.byref(k)) == px.EINVAL
+    assert L.px_autotune_batched(probs, 2, px.F64, 0, None, None, ctypes.byref(k)) == px.EINVAL
+    assert L.px_autotune_batched(over, 2, px.F64, 0, ctx, None, ctypes.byref(k)) == px.EALIAS
 
 
 def test_net_validation(ctx):
