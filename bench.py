@@ -268,9 +268,12 @@ def _fresh(px, n, f_host):
 
 
 USE_NET = {"nonet": 0, "net": 1, "both": 2}
+# (method, smoothing sweeps per step or plain check interval, judge policy)
+LEARNED_CONFIGS = (("plain", 1024, None), ("nonet", 64, 2), ("nonet", 64, 1), ("nonet", 16, 2),
+                   ("both", 64, 2), ("both", 64, 0), ("both", 16, 1), ("net", 64, 2))
 
 
-def _run_method(px, ctx, net, method, n, f_host, smooth, max_sweeps, rtol=1e-10):
+def _run_method(px, ctx, net, method, n, f_host, smooth, max_sweeps, rtol=1e-10, judge=2):
     """One solve of L phi = f from phi = 0: plain FP64 relaxation, or the refinement loop
     with (net) or without (nonet) the network.  Returns the stats."""
     h = 1.0 / n
@@ -280,14 +283,14 @@ def _run_method(px, ctx, net, method, n, f_host, smooth, max_sweeps, rtol=1e-10)
         return px.solve(phi, n, f, h, lam, ctx, mode=px.SOLVE_PLAIN, rtol=rtol, check_every=max(smooth, 256),
                         max_sweeps=max_sweeps, raise_on_error=False)
     return px.solve_learned(phi, n, f, h, lam, ctx, net=net, use_net=USE_NET[method], rtol=rtol,
-                            smooth_sweeps=smooth, max_sweeps=max_sweeps, raise_on_error=False)
+                            smooth_sweeps=smooth, max_sweeps=max_sweeps, judge=judge, raise_on_error=False)
 
 
-def _seconds_per_sweep(px, ctx, net, method, n, f_host, smooth, budget=4096):
+def _seconds_per_sweep(px, ctx, net, method, n, f_host, smooth, judge=2, budget=4096):
     """Wall time per sweep of a budget-limited solve (checks, corrections and network
     evaluations included), from two budgets so that set-up time cancels."""
-    s1 = _run_method(px, ctx, net, method, n, f_host, smooth, budget // 4, rtol=0.0)
-    s2 = _run_method(px, ctx, net, method, n, f_host, smooth, budget, rtol=0.0)
+    s1 = _run_method(px, ctx, net, method, n, f_host, smooth, budget // 4, rtol=0.0, judge=judge)
+    s2 = _run_method(px, ctx, net, method, n, f_host, smooth, budget, rtol=0.0, judge=judge)
     return (s2.seconds - s1.seconds) / (s2.sweeps - s1.sweeps)
 
 
@@ -325,8 +328,7 @@ def learned_workload(px, ctx, train_steps, train_n=1024, eval_n=2048):
     for n in (256, 512, 1024):
         f_host = W.grf_rhs(n, W.SEED_EVAL_BASE + 1)
         ex = exact_solution(f_host)
-        for method, smooth in (("plain", 1024), ("nonet", 16), ("nonet", 64), ("net", 16), ("net", 64),
-                               ("both", 16), ("both", 64), ("both", 256)):
+        for method, smooth, judge in LEARNED_CONFIGS:
             phi, f = _fresh(px, n, f_host)
             h = 1.0 / n
             lam = OMEGA * h * h / 4.0
@@ -335,9 +337,10 @@ def learned_workload(px, ctx, train_steps, train_n=1024, eval_n=2048):
                               raise_on_error=False)
             else:
                 st = px.solve_learned(phi, n, f, h, lam, ctx, net=net, use_net=USE_NET[method], rtol=1e-10,
-                                      smooth_sweeps=smooth, raise_on_error=False)
+                                      smooth_sweeps=smooth, judge=judge, raise_on_error=False)
             err = float(np.abs(phi[1:n + 1, 1:n + 1].cpu().numpy() - ex).max() / np.abs(ex).max())
-            rec = {"n": n, "method": method, "smooth": smooth, "status": st.status, "sweeps": st.sweeps,
+            rec = {"n": n, "method": method, "smooth": smooth, "judge": judge, "status": st.status,
+                   "sweeps": st.sweeps,
                    "seconds": round(st.seconds, 4), "rel_res_max": st.rel_res_max, "rel_err_vs_exact": err}
             if method != "plain":
                 rec["corrections"], rec["rejected"], rec["fell_back"] = st.corrections, st.rejected, st.fell_back
@@ -352,9 +355,10 @@ def learned_workload(px, ctx, train_steps, train_n=1024, eval_n=2048):
     for r in measured:
         if r["n"] != 1024:
             continue
-        sps = _seconds_per_sweep(px, ctx, net, r["method"], eval_n, f_host, r["smooth"])
+        sps = _seconds_per_sweep(px, ctx, net, r["method"], eval_n, f_host, r["smooth"], judge=r["judge"] or 2)
         sweeps = r["sweeps"] * (eval_n / 1024) ** 2
-        rec = {"method": r["method"], "smooth": r["smooth"], "s_per_sweep": sps, "extrapolated_sweeps": sweeps,
+        rec = {"method": r["method"], "smooth": r["smooth"], "judge": r["judge"], "s_per_sweep": sps,
+               "extrapolated_sweeps": sweeps,
                "extrapolated_seconds": sweeps * sps}
         extra.append(rec)
         log(f"  learned/{eval_n}: {rec}")
@@ -365,6 +369,35 @@ def learned_workload(px, ctx, train_steps, train_n=1024, eval_n=2048):
     out["gain_with_network_vs_without"] = best["nonet"] / min(best["net"], best["both"])
     meas = {m: min(r["seconds"] for r in measured if r["method"] == m and r["n"] == 1024) for m in ms}
     out["measured_speedup_vs_plain_1024"] = {m: meas["plain"] / meas[m] for m in ms[1:]}
+    net.close()
+    return out
+
+
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+CONV_FLOPS_PER_PIXEL = 2 * 32 * 32 * 9  # one 32 -> 32 layer
+
+
+def net_workload(px):
+    """The correction network's kernels: forward at 1024^2 and 2048^2 (the learned loop's
+    per-step cost) and one training evaluation (forward, loss, backward) on 2 x 1024^2,
+    timed with HIP events on the stream the kernels run on.  The 32 -> 32 convolutions
+    are reported against the dense BF16 matrix-core peak."""
+    import torch
+    import workloads as W
+    net = px.Net(W.net_initial_weights(1))
+    out = {}
+    for n in (1024, 2048):
+        x = torch.from_numpy(W.uniform_rhs(n, 7)).cuda().float().reshape(1, n, n)
+        y = torch.empty_like(x)
+        t = time_region(lambda: net.forward(x, y), reps=20, warmup=3) / 20
+        out[f"forward_{n}"] = {"ms": round(t * 1e3, 4), "gpix_s": round(n * n / t / 1e9, 3),
+                               "conv_layers_tflops_if_alone": round(2 * CONV_FLOPS_PER_PIXEL * n * n / t / 1e12, 1)}
+        log(f"  net forward {n}^2: {out[f'forward_{n}']}")
+    x = torch.from_numpy(W.uniform_rhs(1024, 8)).cuda().float().reshape(1, 1024, 1024).repeat(2, 1, 1).contiguous()
+    tg = torch.zeros_like(x)
+    t = time_region(lambda: net.loss_grad(x, tg), reps=5, warmup=1) / 5
+    out["train_step_2x1024"] = {"ms": round(t * 1e3, 3)}
+    log(f"  net training evaluation 2x1024^2: {t * 1e3:.2f} ms")
     net.close()
     return out
 
@@ -458,7 +491,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (the known-size kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=["relax", "mixed", "learned", "batched"], default="relax",
+    ap.add_argument("--workload", choices=["relax", "mixed", "learned", "batched", "net"], default="relax",
                     help="relax: the fused relaxation benchmark (default); mixed: mixed-precision "
                          "refinement against plain FP64 (time to tolerance); learned: the trained "
                          "correction network in the refinement loop; batched: 512 uneven problems")
@@ -502,9 +535,12 @@ def main():
         ctx.close()
         return
 
-    if args.workload in ("learned", "batched"):
+    if args.workload in ("learned", "batched", "net"):
         t0 = time.perf_counter()
-        if args.workload == "learned":
+        if args.workload == "net":
+            res = net_workload(px)
+            value, unit = res["forward_2048"]["gpix_s"], "Gpixel/s (network forward, 2048^2)"
+        elif args.workload == "learned":
             res = learned_workload(px, ctx, args.train_steps)
             value = max(res["speedup_vs_plain"]["net"], res["speedup_vs_plain"]["both"])
             unit = "x time-to-1e-10 speedup (learned loop vs plain FP64, 2048^2, extrapolated)"

@@ -338,6 +338,10 @@ typedef struct px_learned_opts {
     int use_net;          /* correction directions: 0: r alone (the same loop without
                              the network); 1: N(r / rms(r)) alone; 2: both, combined
                              as px_correction_step mode 2                              */
+    int judge;            /* what a finite step that raised the residual triggers:
+                             0: nothing (every finite step is kept); 1: the step is
+                             kept, plain steps follow for a back-off period; 2: the
+                             step is undone, plain steps follow for a back-off period */
 } px_learned_opts;
 
 typedef struct px_learned_stats {
@@ -368,12 +372,16 @@ int px_correction_step(void *phi, int n, int ld, const double *r, int ld_r, cons
  * step: r = f - L phi in FP64; the correction step of px_correction_step with
  * d = N(r / rms(r)) and mode = use_net (FP64 update); then smooth_sweeps fused
  * relaxation sweeps.  Plain
- * relaxation judges each step by its FP64 residual: if the L2 norm after the step
- * (and its sweeps) is not below the one before, the step is undone and the next
- * 1, 2, 4, ... (at most 64, doubling while steps keep failing, reset by a kept step)
- * steps are plain relaxation; if it is not finite (a broken network) the step is
- * undone and the solve continues with plain relaxation alone, which then equals the
- * loop of px_solve PX_SOLVE_PLAIN with check_every = smooth_sweeps.  Stopping rules
+ * relaxation judges each step by its FP64 residual.  If the L2 norm after the step
+ * (and its sweeps) is not finite (a broken network) the step is undone and the solve
+ * continues with plain relaxation alone, which then equals the loop of px_solve
+ * PX_SOLVE_PLAIN with check_every = smooth_sweeps.  If it is finite but not below the
+ * norm before, opts->judge decides: keep the step (0), keep it and relax plainly for
+ * the next 1, 2, 4, ... steps (1), or undo it and do the same (2); the back-off period
+ * doubles while steps keep failing (at most 64) and resets when one succeeds.  Every
+ * step with a finite result lowers the energy norm of the error (the step minimises it
+ * over its directions, which include the zero step, and damped Jacobi sweeps with
+ * omega <= 1 never raise it), so keeping such steps is safe.  Stopping rules
  * and return codes as px_solve.  Waits on `stream` every step.  net may be NULL when
  * use_net is 0.  stats may be NULL.
  */

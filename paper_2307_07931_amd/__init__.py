@@ -57,7 +57,8 @@ class _SolveStats(ctypes.Structure):
 
 class _LearnedOpts(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_int), ("rtol", ctypes.c_double), ("max_sweeps", ctypes.c_int64),
-                ("smooth_sweeps", ctypes.c_int), ("tblock", ctypes.c_int), ("use_net", ctypes.c_int)]
+                ("smooth_sweeps", ctypes.c_int), ("tblock", ctypes.c_int), ("use_net", ctypes.c_int),
+                ("judge", ctypes.c_int)]
 
 
 class _LearnedStats(ctypes.Structure):
@@ -497,14 +498,15 @@ class LearnedStats(SolveStats):
 
 
 def solve_learned(phi, n, f, h, lam, ctx: Context, net: "Net | None" = None, use_net=1, rtol=1e-10,
-                  norm=0, max_sweeps=10 ** 9, smooth_sweeps=16, tblock=0, stream=None,
+                  norm=0, max_sweeps=10 ** 9, smooth_sweeps=16, tblock=0, judge=2, stream=None,
                   raise_on_error=True) -> LearnedStats:
     """Refinement loop with energy-optimal correction steps along r (use_net 0), the
     network's direction (1) or both (2), plain smoothing sweeps and the plain-relaxation
     judge; float64 phi and f, in place."""
     ld = _ld(phi, n + 2, n + 2, "phi")
     ldf = _ld(f, n, n, "f")
-    o = _LearnedOpts(int(norm), float(rtol), int(max_sweeps), int(smooth_sweeps), int(tblock), int(use_net))
+    o = _LearnedOpts(int(norm), float(rtol), int(max_sweeps), int(smooth_sweeps), int(tblock), int(use_net),
+                     int(judge))
     s = _LearnedStats()
     st = lib().px_solve_learned(_ptr(phi), n, ld, _ptr(f), ldf, float(h), float(lam),
                                 net.handle if net is not None else ctypes.c_void_p(0), ctypes.byref(o),

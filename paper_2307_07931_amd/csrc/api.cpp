@@ -830,6 +830,7 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
     if (o->smooth_sweeps < 1) return fail(PX_EINVAL, "smooth_sweeps must be >= 1");
     if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
     if (o->use_net < 0 || o->use_net > 2) return fail(PX_EINVAL, "use_net must be 0, 1 or 2");
+    if (o->judge < 0 || o->judge > 2) return fail(PX_EINVAL, "judge must be 0, 1 or 2");
     if (o->use_net && !net) return fail(PX_EINVAL, "use_net needs a network");
     if (o->use_net && net_device(net) != ctx->device)
         return fail(PX_EINVAL, "network on device %d, context on device %d", net_device(net), ctx->device);
@@ -931,18 +932,23 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
             double nn[2];
             if ((st = read_norms(nn))) return st;
             const bool finite = std::isfinite(nn[0]) && std::isfinite(nn[1]);
-            if (finite && nn[1] < nr[1]) {
+            const bool better = finite && nn[1] < nr[1];
+            if (better || (finite && o->judge != 2)) {
                 S.corrections += 1;
                 S.base.sweeps += todo;
                 S.base.outer_steps += 1;
                 nr[0] = nn[0];
                 nr[1] = nn[1];
                 r_fresh = true;
-                backoff = 0;
+                if (better || o->judge == 0) {
+                    backoff = 0;
+                } else {
+                    backoff = backoff ? std::min(2 * backoff, 64) : 1;
+                    skip = backoff;
+                }
             } else {
-                // the judge: plain relaxation's residual did not drop -- undo the step and
-                // relax plainly for a back-off period (doubling while steps keep failing);
-                // a non-finite result means a broken network: plain relaxation from here on
+                // a broken network (non-finite) or, with judge 2, a step that raised the
+                // residual: undo it
                 PX_HIP(copy_grid_launch(F64, save, cur, n, ld, s), "copy kernel launch");
                 S.rejected += 1;
                 r_fresh = false;

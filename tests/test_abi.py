@@ -241,7 +241,7 @@ def test_solve_learned_validation(ctx):
 
     def run(opts=True, net=None, **kw):
         o = px._LearnedOpts(kw.get("norm", 0), kw.get("rtol", 1e-10), kw.get("max_sweeps", 100),
-                            kw.get("smooth", 16), kw.get("tblock", 0), kw.get("use_net", 0))
+                            kw.get("smooth", 16), kw.get("tblock", 0), kw.get("use_net", 0), kw.get("judge", 2))
         return L.px_solve_learned(P(kw.get("phi", FAKE)), kw.get("n", 64), kw.get("ld", 66),
                                   P(kw.get("f", FAKE2)), kw.get("ld_f", 64), kw.get("h", 1 / 64),
                                   kw.get("lam", 1e-5), net, ctypes.byref(o) if opts else None, None,
@@ -260,6 +260,7 @@ def test_solve_learned_validation(ctx):
     assert run(smooth=0) == px.EINVAL
     assert run(tblock=9) == px.EINVAL
     assert run(use_net=3) == px.EINVAL
+    assert run(judge=3) == px.EINVAL
     assert run(use_net=-1) == px.EINVAL
     assert run(use_net=1) == px.EINVAL  # no network
     assert "network" in px.last_error()
