@@ -22,14 +22,11 @@ struct bf16 {
     uint16_t bits;
 };
 
-// Round-to-nearest-even of a binary32 to bfloat16 (quiet NaN kept NaN).
-__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
-{
-    uint32_t u = __float_as_uint(x);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
+// Round-to-nearest-even of a binary32 to bfloat16: gfx950's v_cvt_pk_bf16_f32, which
+// rounds ties to even, keeps denormals, and turns a NaN into a quiet NaN with its sign and
+// upper payload bits ((bits >> 16) | 0x40) -- checked on the device against the integer
+// formulation over every upper half-word with tie, near-tie and zero lower half-words.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
 // Storage traits: A is the arithmetic type, load/store convert, round() gives the

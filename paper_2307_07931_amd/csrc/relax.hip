@@ -13,12 +13,19 @@ inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_
 int relax_default_rows(int dtype, int n, int sweeps)
 {
     // Measured on MI355X at 4096^2: short bands win (more waves in flight); the
-    // recomputed halo rows (about 2*sweeps per band) favour 32 rows at 5-8 sweeps.
+    // recomputed halo rows (about 2*sweeps per band) favour about 32 rows at 5-8 sweeps.
+    // With sweeps + 1 a multiple of 3 the interior loop runs in blocks of sweeps + 1
+    // steps, so the band height is chosen with rows + 2*sweeps a multiple of sweeps + 1.
     int rows;
     if (dtype == F64)
         rows = sweeps <= 4 ? 16 : 32;
     else
         rows = (sweeps == 3 || sweeps == 4) ? 16 : 32;
+    if ((sweeps + 1) % 3 == 0) {
+        const int u = sweeps + 1;
+        rows -= (rows + 2 * sweeps) % u;  // largest such height not above the heuristic
+        if (rows < 8) rows += u;
+    }
     const int cap = std::max(8, (n + 2) / 8);
     return std::min(rows, cap);
 }

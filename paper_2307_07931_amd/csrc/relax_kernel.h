@@ -86,16 +86,17 @@ struct KArgs {
 constexpr int DPP_WAVE_SHR1 = 0x138;
 constexpr int DPP_WAVE_SHL1 = 0x130;
 
+// bound_ctrl: a lane without a source lane is written 0 (no "old" value to set up).
 template <int CTRL>
 __device__ __forceinline__ float dpp_shift(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xf, 0xf, true));
 }
 template <int CTRL>
 __device__ __forceinline__ double dpp_shift(double x)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 template <typename A> __device__ __forceinline__ A lane_from_left(A x) { return dpp_shift<DPP_WAVE_SHR1>(x); }
@@ -480,6 +481,98 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 
 }
 
+// Interior tiles of launches without norms whose K + 1 is a multiple of 3 (K = 2, 5, 8):
+// the step loop is unrolled U = K + 1 times, so the 3-row windows of every level (3 | U),
+// the (K + 1)-row ring of f (U rows) and a 3-deep ring of prefetched rows all rotate by
+// renaming: row x of a level lives in slot (x - sb) mod 3, f of phi row x in slot
+// (x - sb) mod U.  The arithmetic and its order are those of run_tile; only where values
+// are kept differs.  The step count is rounded up to a multiple of U (the extra steps
+// compute rows past the band and store nothing).
+template <typename T, int V, int K, bool VEC>
+__device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
+{
+    using E = Elem<T>;
+    using A = typename E::A;
+    using IO = Io<T, V, VEC>;
+    using Raw = typename IO::Raw;
+    constexpr int U = K + 1;
+    constexpr int PR = 3;
+    static_assert(U % 3 == 0, "window slots must repeat within the unrolled steps");
+    constexpr int ES = (int)sizeof(T);
+    const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
+    const int rb = p.ld * ES, rbf = p.ld_f * ES;
+    const A w = (A)p.w, lam = (A)p.lam;
+
+    A win[K][3][V];
+    A fr[U][V];
+#pragma unroll
+    for (int t = 0; t < K; ++t)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int v = 0; v < V; ++v) win[t][k][v] = 0;
+#pragma unroll
+    for (int j = 0; j < U; ++j)
+#pragma unroll
+        for (int v = 0; v < V; ++v) fr[j][v] = 0;
+    const int fc = VEC ? mc : mc - 1;
+    const int sb = y0 - K, se = sb + (y1 - y0 + 2 * K + U - 1) / U * U;
+    Raw pf[PR], pff[PR];
+#pragma unroll
+    for (int q = 0; q < PR; ++q) {
+        pf[q] = IO::load(row_rsrc(p.in, sb + q, n + 2, rb), mc);
+        pff[q] = IO::load(row_rsrc(p.f, sb + q - 1, n, rbf), fc);
+    }
+    for (int s0 = sb; s0 < se; s0 += U) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int s = s0 + q;
+            IO::unpack(pf[q % PR], win[0][q % 3]);
+            {
+                A fo[V];
+                IO::unpack(pff[q % PR], fo);
+                if constexpr (VEC) {
+                    fr[q][0] = lane_from_left(fo[V - 1]);
+#pragma unroll
+                    for (int v = 1; v < V; ++v) fr[q][v] = fo[v - 1];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) fr[q][v] = fo[v];
+                }
+            }
+            pf[q % PR] = IO::load(row_rsrc(p.in, s + PR, n + 2, rb), mc);
+            pff[q % PR] = IO::load(row_rsrc(p.f, s + PR - 1, n, rbf), fc);
+#pragma unroll
+            for (int t = 1; t <= K; ++t) {
+                if (s < y0 - K + 2 * t) break;  // rows this level does not need yet
+                const int r = s - t;
+                constexpr int M3 = 3 * U;  // keeps the slot arithmetic non-negative
+                const int sn = (q - t - 1 + M3) % 3, sc = (q - t + M3) % 3, ss = (q - t + 1 + M3) % 3;
+                const int sf = (q - t + U) % U;
+                const A left = lane_from_left(win[t - 1][sc][V - 1]);
+                const A right = lane_from_right(win[t - 1][sc][0]);
+                A nv[V];
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const A C = win[t - 1][sc][v];
+                    const A N = win[t - 1][sn][v];
+                    const A S = win[t - 1][ss][v];
+                    const A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
+                    const A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
+                    const A st = (((N - (A)4 * C) + Wn) + En) + S;
+                    nv[v] = E::round((C + w * st) - lam * fr[sf][v]);
+                }
+                if (t < K) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
+                } else if (r >= y0 && r < y1) {
+                    store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv, false);
+                }
+            }
+        }
+    }
+}
+
 // One wave tile of one problem: geometry, interior/edge dispatch, streaming loop.
 template <typename T, int V, int K, int RM, int PF, bool VEC>
 __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lane, unsigned long long &rmax,
@@ -498,6 +591,12 @@ __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lan
     // interior tile: loaded columns and needed rows all inside [1, n]
     const bool interior = c0 >= 1 && c0 + WAVE * V - 1 <= n && y0 - NL >= 1 && y1 + NL - 1 <= n;
     const Tile tl{n, oc0, oc1, mc, y0, y1, whole};
+    if constexpr (RM == RES_NONE && (K + 1) % 3 == 0) {
+        if (interior) {
+            run_tile_renamed<T, V, K, VEC>(p, tl);
+            return;
+        }
+    }
     if (interior)
         run_tile<T, V, K, RM, PF, VEC, false>(p, tl, rmax, rsum);
     else

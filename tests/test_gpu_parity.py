@@ -252,3 +252,27 @@ def test_unfused_sweep_equals_fused(ctx, dt):
     inner[1:n + 1, 1:n + 1] = True  # the in-place update leaves ghosts alone
     H.assert_grid_bitwise(un, g, n, mask=inner)
     assert float(norms[0]) == nf[0]
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("k", [2, 5, 8])
+def test_interior_unrolled_path_matches_oracle(dt, k):
+    """Interior tiles of launches without norms with k + 1 a multiple of 3 run the
+    unrolled-ring loop; on a grid with interior tiles in every direction, several launches
+    (the last one with final norms) at band heights that do and do not fill whole unrolled
+    blocks give the oracle's result bit for bit."""
+    H.require_gpu()
+    n = 333
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    phi0 = W.uniform_phi(n, 600 + k)
+    f = W.uniform_rhs(n, 610 + k)
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, 3 * k + 1, dt)
+    for rows in (8, 14, 29):
+        c = px.Context()
+        c.set_tile_rows(rows)
+        print(f"case: {dt} k={k} rows={rows}", flush=True)
+        got, nm = H.gpu_relax(phi0, f, n, h, lam, 3 * k + 1, dt, c, tblock=k)
+        H.assert_grid_bitwise(got, ref, n, what=f"{dt} k={k} rows={rows}")
+        H.assert_norms(nm, mx, sq, n=n)
+        c.close()
