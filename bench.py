@@ -44,11 +44,12 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
-TRAFFIC_SHA256 = "6aab2985c41c23025e537a846a976322ac3b79473b759d7cec3e867bbf4b43a1"
+TRAFFIC_SHA256 = "0fe94db4060853a24ca851a2dd121cd3c05fa7bdbe99c9ffb939b9f80ce13309"
 TRAFFIC_SCALE = (1048576.0 / 524302.76, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 16): (272325.66, 131286.32), (8, 20): (247775.35, 131283.18), (8, 24): (230834.62, 131280.91),
-    (8, 28): (219077.19, 131279.61), (8, 32): (208242.93, 131278.29), (1, 16): (167072.05, 132517.95),
+    (8, 20): (236779.65, 131282.43), (8, 24): (247089.08, 131279.99), (8, 28): (218492.70, 131277.75),
+    (8, 29): (211965.86, 131277.99), (8, 32): (223959.30, 131278.37), (8, 38): (192628.13, 131275.83),
+    (1, 16): (167084.32, 132516.75),
 }
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
