@@ -274,7 +274,7 @@ KArgs make_kargs(int dtype, const void *in, void *out, const void *f, int n, int
 {
     const int V = dtype == F64 ? 2 : 4;
     const int NL = k + (rm == RES_FINAL ? 1 : 0);
-    const int halo = (NL + V - 1) / V * V;
+    const Geometry g = make_geometry(V, n, NL, rows);  // the kernel assumes this geometry
     KArgs a;
     std::memset(&a, 0, sizeof a);
     a.in = in;
@@ -287,12 +287,12 @@ KArgs make_kargs(int dtype, const void *in, void *out, const void *f, int n, int
     a.c = 1.0 / (h * h);
     a.w = lambda / (h * h);
     a.lam = lambda;
-    a.halo = halo;
-    a.col_origin = 0;
-    a.stride = 64 * V - 2 * halo;
-    a.tiles_x = (n + 2 + a.stride - 1) / a.stride;
-    a.rows = rows;
-    a.ntiles = a.tiles_x * ((n + 2 + rows - 1) / rows);
+    a.halo = g.halo;
+    a.col_origin = g.col_origin;
+    a.stride = g.stride;
+    a.tiles_x = g.tiles_x;
+    a.rows = g.rows;
+    a.ntiles = g.ntiles;
     return a;
 }
 

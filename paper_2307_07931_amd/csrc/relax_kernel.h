@@ -58,7 +58,10 @@ struct Geometry {
 inline Geometry make_geometry(int V, int n, int NL, int rows)
 {
     Geometry g;
-    g.halo = (NL + V - 1) / V * V;
+    // one pipeline level: no overlap -- waves own disjoint, 64 V-column strips that start on
+    // 64 V-element boundaries, and the two columns beyond a strip come from single-element
+    // loads (run_tile); deeper pipelines recompute a halo of NL columns, rounded to V
+    g.halo = NL == 1 ? 0 : (NL + V - 1) / V * V;
     g.col_origin = 0;
     g.stride = WAVE * V - 2 * g.halo;
     g.tiles_x = (n + 2 + g.stride - 1) / g.stride;
@@ -245,6 +248,29 @@ template <int V> struct Io<bf16, V, false> {
     }
 };
 
+// Single-element load of column col (OOB: 0), as the arithmetic type.
+template <typename T> struct Load1;
+template <> struct Load1<double> {
+    __device__ static double ld(__amdgpu_buffer_rsrc_t r, int col)
+    {
+        const u32x2 u = __builtin_amdgcn_raw_buffer_load_b64(r, col == OOB ? OOB : col * 8, 0, 0);
+        return __hiloint2double((int)u.y, (int)u.x);
+    }
+};
+template <> struct Load1<float> {
+    __device__ static float ld(__amdgpu_buffer_rsrc_t r, int col)
+    {
+        return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, col == OOB ? OOB : col * 4, 0, 0));
+    }
+};
+template <> struct Load1<bf16> {
+    __device__ static float ld(__amdgpu_buffer_rsrc_t r, int col)
+    {
+        return __uint_as_float((unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, col == OOB ? OOB : col * 2, 0, 0)
+                               << 16);
+    }
+};
+
 // Single-element masked store (edge tiles, ghost cells).
 __device__ __forceinline__ void store1(__amdgpu_buffer_rsrc_t r, int col, bool ok, double x)
 {
@@ -315,7 +341,17 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
     constexpr int RL = (RM == RES_FINAL) ? K + 1 : K;
     constexpr int FQ = RL + 1;
     constexpr int ES = (int)sizeof(T);
+    // one level, no halo: the strip's outer neighbours come from single-element loads of
+    // each row (lane 0 the column left of the strip, the last lane the one right of it), and
+    // lane 0's f of its first column (which the one-column shift of f would take from the
+    // strip to the left) from one more
+    constexpr bool NH = (NL == 1);
     const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int c0 = mc - lane * V;
+    const int ecol = (lane == 0) ? (c0 >= 1 ? c0 - 1 : OOB) : (lane == WAVE - 1 ? c0 + WAVE * V : OOB);
+    // f is compact: f column j - 1 belongs to phi column j
+    const int efcol = (VEC && lane == 0 && c0 >= 1) ? c0 - 1 : OOB;
     const bool whole = tl.whole;
     const bool dir = (p.bc == DIRICHLET0);
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
@@ -348,10 +384,16 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
     // rows past the band and store nothing, and the loop keeps a single latch)
     const int sb = y0 - NL, se = sb + (y1 - y0 + 2 * NL + PF - 1) / PF * PF;
     Raw pf[PF], pff[PF];
+    A pe[NH ? PF : 1], pfe[NH ? PF : 1];  // single-element loads of the rows in flight
+    A ex1 = 0, ex2 = 0;                    // single elements of rows s - 1, s
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
         pf[q] = IO::load(row_rsrc(p.in, sb + q, n + 2, rb), mc);
         pff[q] = IO::load(row_rsrc(p.f, sb + q - 1, n, rbf), fc);
+        if constexpr (NH) {
+            pe[q] = Load1<T>::ld(row_rsrc(p.in, sb + q, n + 2, rb), ecol);
+            pfe[q] = Load1<T>::ld(row_rsrc(p.f, sb + q - 1, n, rbf), efcol);
+        }
     }
     for (int s0 = sb; s0 < se; s0 += PF) {
 #pragma unroll
@@ -364,6 +406,10 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                 win[0][1][v] = win[0][2][v];
             }
             IO::unpack(pf[q], win[0][2]);
+            if constexpr (NH) {
+                ex1 = ex2;
+                ex2 = pe[q];
+            }
 #pragma unroll
             for (int j = FQ - 1; j > 0; --j)
 #pragma unroll
@@ -372,7 +418,8 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                 A fo[V];
                 IO::unpack(pff[q], fo);
                 if constexpr (VEC) {
-                    fq[0][0] = lane_from_left(fo[V - 1]);
+                    const A sh = lane_from_left(fo[V - 1]);
+                    fq[0][0] = (NH && lane == 0) ? pfe[NH ? q : 0] : sh;
 #pragma unroll
                     for (int v = 1; v < V; ++v) fq[0][v] = fo[v - 1];
                 } else {
@@ -382,14 +429,22 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
             }
             pf[q] = IO::load(row_rsrc(p.in, s + PF, n + 2, rb), mc);
             pff[q] = IO::load(row_rsrc(p.f, s + PF - 1, n, rbf), fc);
+            if constexpr (NH) {
+                pe[q] = Load1<T>::ld(row_rsrc(p.in, s + PF, n + 2, rb), ecol);
+                pfe[q] = Load1<T>::ld(row_rsrc(p.f, s + PF - 1, n, rbf), efcol);
+            }
 
             // ---- levels 1..NL, level t at row s - t
 #pragma unroll
             for (int t = 1; t <= NL; ++t) {
                 if (s < y0 - NL + 2 * t) break;  // rows this level does not need yet
                 const int r = s - t;
-                const A left = lane_from_left(win[t - 1][1][V - 1]);
-                const A right = lane_from_right(win[t - 1][1][0]);
+                A left = lane_from_left(win[t - 1][1][V - 1]);
+                A right = lane_from_right(win[t - 1][1][0]);
+                if constexpr (NH) {
+                    left = lane == 0 ? ex1 : left;
+                    right = lane == WAVE - 1 ? ex1 : right;
+                }
                 A st[V];
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
