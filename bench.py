@@ -182,6 +182,21 @@ def slowest_mode_factor(n):
     return 1.0 - OMEGA * 2.0 * math.sin(math.pi / (2 * n)) ** 2
 
 
+def tune_sizes(px, ctx, n, f_host, dtypes=("f64", "f32", "bf16")):
+    """Autotunes the relaxation for n^2 grids of each element type (the grids the solvers
+    use have the same pitch), so that small, latency-bound grids get short bands."""
+    import torch
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
+    for dt in dtypes:
+        a = px.alloc_grid(n, tdt[dt])
+        b = px.alloc_grid(n, tdt[dt])
+        f = px.alloc_rhs(n, tdt[dt])
+        src = torch.from_numpy(f_host).cuda()
+        f[:, :n] = src if dt == "f64" else src.float().to(tdt[dt])
+        k, rows, g = px.autotune(a, b, n, f, ctx)
+        log(f"  tuned {n}^2 {dt}: k={k} rows={rows} ({g:.1f} Gcell/s)")
+
+
 def mixed_workload(px, ctx):
     """Mixed-precision refinement (FP32 / BF16 inner sweeps, FP64 outer residual and
     update) against plain FP64 relaxation, on |k|^-2 Gaussian-random-field right-hand
@@ -199,6 +214,7 @@ def mixed_workload(px, ctx):
         ex = exact_solution(f_host)
         h = 1.0 / n
         lam = OMEGA * h * h / 4.0
+        tune_sizes(px, ctx, n, f_host)
         for mode, name, inner in ((px.SOLVE_PLAIN, "plain_f64", 0), (px.SOLVE_MIXED_F32, "mixed_f32", 64),
                                   (px.SOLVE_MIXED_BF16, "mixed_bf16", 32)):
             phi = px.alloc_grid(n, torch.float64)
@@ -329,6 +345,7 @@ def learned_workload(px, ctx, train_steps, train_n=1024, eval_n=2048):
     for n in (256, 512, 1024):
         f_host = W.grf_rhs(n, W.SEED_EVAL_BASE + 1)
         ex = exact_solution(f_host)
+        tune_sizes(px, ctx, n, f_host, dtypes=("f64",))
         for method, smooth, judge in LEARNED_CONFIGS:
             phi, f = _fresh(px, n, f_host)
             h = 1.0 / n

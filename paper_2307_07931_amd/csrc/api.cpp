@@ -591,6 +591,39 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
         const int per_line = 128 / elem_size(lowp);
         const int ldl = (n + 2 + per_line - 1) / per_line * per_line;
         const int k_in = o->tblock ? o->tblock : default_tblock(ctx, lowp, n, ldl);
+        // Grids up to 1024^2 are launch-bound: there the solve runs as a batch of one,
+        // whose outer steps are replayed from a captured graph with the convergence test on
+        // the device (same arithmetic and stopping rules, identical results).  It needs rows
+        // of phi and f on 16-byte boundaries.
+        const bool graph_ok = n <= 1024 && reinterpret_cast<uintptr_t>(phi) % 16 == 0 &&
+                              reinterpret_cast<uintptr_t>(f) % 16 == 0 && (ld * 8) % 16 == 0 &&
+                              (ld_f * 8) % 16 == 0;
+        if (graph_ok) {
+            if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+            if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
+            BatchProblem bp{phi, f, n, ld, ld_f, h, lambda};
+            BatchStat bs;
+            char err[256] = "";
+            st = batch_solve(*ctx->batch, lowp, &bp, 1, bc, o->rtol, o->norm, o->max_sweeps, inner,
+                             std::min(k_in, inner), 8, &bs, s, err, sizeof err);
+            // a problem that did not converge is reported through bs.state below
+            if (st != PX_OK && st != PX_ENOTCONV && st != PX_ENONFINITE && st != PX_EDIVERGED)
+                return fail(st, "%s", err);
+            S.sweeps = bs.sweeps;
+            S.outer_steps = bs.steps;
+            S.res_max = bs.res_max;
+            S.res_l2 = bs.res_l2;
+            S.rel_res_max = bs.rel_res_max;
+            S.rel_res_l2 = bs.rel_res_l2;
+            S.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (stats) *stats = S;
+            switch (bs.state) {
+            case 0: return PX_OK;
+            case -1: return fail(PX_ENOTCONV, "max_sweeps reached (rel res %g)", o->norm ? bs.rel_res_l2 : bs.rel_res_max);
+            case -2: return fail(PX_ENONFINITE, "non-finite residual");
+            default: return fail(PX_EDIVERGED, "residual grew beyond 1e8 times its start");
+            }
+        }
         // host readbacks every `spacing` outer steps (the device computes norms every step)
         const int spacing = o->check_every > inner ? o->check_every / inner : 1;
         const size_t lg = grid_bytes(n, ldl, lowp);

@@ -104,3 +104,44 @@ def test_sweep_budget_is_reported(ctx):
     assert st.status == px.ENOTCONV and st.sweeps == 200
     with pytest.raises(px.ProtoxError):
         px.solve(phi, n, fd, h, lam, ctx, rtol=1e-12, max_sweeps=100, check_every=100)
+
+
+@pytest.mark.parametrize("mode", [px.SOLVE_MIXED_F32, px.SOLVE_MIXED_BF16])
+def test_mixed_graph_path_equals_host_loop(ctx, mode):
+    """Mixed solves of grids up to 1024^2 with 16-byte aligned rows run as a graph-replayed
+    batch of one; a layout that does not qualify runs the host-driven loop.  Same sweeps,
+    outer steps, norms and iterate, bit for bit."""
+    n = 48
+    f = W.grf_rhs(n, 107)
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    phi_a = H.device_grid(np.zeros((n + 2, n + 2)), n, "f64")              # 16-byte rows: graph
+    phi_b = H.device_grid(np.zeros((n + 2, n + 2)), n, "f64", ld=n + 3)    # odd pitch: host loop
+    fd = H.device_rhs(f, n, "f64")
+    a = px.solve(phi_a, n, fd, h, lam, ctx, mode=mode, rtol=1e-9, inner_sweeps=24, tblock=8)
+    b = px.solve(phi_b, n, fd, h, lam, ctx, mode=mode, rtol=1e-9, inner_sweeps=24, tblock=8)
+    assert (a.sweeps, a.outer_steps, a.res_max) == (b.sweeps, b.outer_steps, b.res_max)
+    m = np.zeros((n + 2, n + 2), dtype=bool)
+    m[1:n + 1, 1:n + 1] = True
+    H.assert_grid_bitwise(H.to_storage_np(phi_a, "f64"), H.to_storage_np(phi_b, "f64"), n, mask=m)
+
+
+def test_mixed_failure_statuses(ctx):
+    n = 24
+    h = 1.0 / n
+    f = W.uniform_rhs(n, 108)
+    bad = f.copy()
+    bad[5, 7] = np.nan
+    for layout in (None, n + 3):  # graph path, host loop
+        phi = H.device_grid(np.zeros((n + 2, n + 2)), n, "f64", ld=layout)
+        st = px.solve(phi, n, H.device_rhs(bad, n, "f64"), h, OMEGA * h * h / 4, ctx, mode=px.SOLVE_MIXED_F32,
+                      rtol=1e-8, raise_on_error=False)
+        assert st.status == px.ENONFINITE, layout
+        phi = H.device_grid(np.zeros((n + 2, n + 2)), n, "f64", ld=layout)
+        st = px.solve(phi, n, H.device_rhs(f, n, "f64"), h, OMEGA * h * h / 4, ctx, mode=px.SOLVE_MIXED_F32,
+                      rtol=1e-14, max_sweeps=96, inner_sweeps=32, raise_on_error=False)
+        assert st.status == px.ENOTCONV and st.sweeps == 96, layout
+        phi = H.device_grid(np.zeros((n + 2, n + 2)), n, "f64", ld=layout)
+        st = px.solve(phi, n, H.device_rhs(f, n, "f64"), h, 1.5 * h * h / 4, ctx, mode=px.SOLVE_MIXED_F32,
+                      rtol=1e-14, inner_sweeps=32, raise_on_error=False)
+        assert st.status in (px.EDIVERGED, px.ENONFINITE), (layout, st)
