@@ -403,75 +403,155 @@ __global__ __launch_bounds__(BX) void l4_bwd_kernel(const float *__restrict__ dy
     for (int q = 0; q < 4; ++q) dst[q] = reinterpret_cast<const uint4 *>(out)[q];
 }
 
-// Weight gradient of a 32->32 layer, split over WG_BLOCKS pixel ranges:
-// part[blk][(co*32 + ci)*9 + t] = sum_{p in range} dz[p][co] * act[p + off_t][ci].
-// Thread (ci = tid % 32, co = 4*(tid/32) .. +3) keeps 36 sums.
-__global__ __launch_bounds__(BX) void wgrad32_kernel(const bf16 *__restrict__ act, const bf16 *__restrict__ dz,
-                                                     float *__restrict__ part, int B, int H, int W)
+// Weight gradient of a 32 -> 32 layer on the matrix cores:
+//   dW[co][ci][t] = sum_p dz[p][co] act[p + (a - 1, c - 1)][ci],   t = 3a + c.
+// With q = p + (0, c - 1) the sum runs over q with dz[q - (0, c - 1)] and act[q + (a - 1, 0)]:
+// the column shift moves to dz, so the activation operand is read at aligned pixels (terms
+// with q outside [0, W) meet the zero padding of act).  Per tap it is a 32 x 32 GEMM over
+// pixels, K = pixels, which the matrix cores read 8 consecutive K values per lane: the wave
+// stages its operands in LDS channel-major.  A wave (one per block) owns a 64-pixel column
+// strip of WG_ROWS image rows; per row i it stages activation row i + 1 (rows i - 1, i, i + 1
+// form a ring) and dz row i in three copies shifted by c - 1, then runs 9 taps x 4 chunks of
+// 16 pixels = 36 v_mfma_f32_32x32x16_bf16 into 9 accumulator tiles.  Blocks take work units
+// in a fixed order and write one partial each; a second pass sums them in block order.
+constexpr int WGP = 72;        // pixels per channel row in LDS (64 + pad: conflict-free reads)
+constexpr int WG_ROWS = 16;    // image rows per work unit
+constexpr int WGM_BLOCKS = 2048;
+
+__global__ __launch_bounds__(64) void wgrad32_mfma_kernel(const bf16 *__restrict__ act,
+                                                          const bf16 *__restrict__ dz, float *__restrict__ part,
+                                                          int B, int H, int W)
 {
-    const long long N = (long long)B * H * W;
-    const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
-    const int ci = threadIdx.x & 31, cq = (threadIdx.x >> 5) * 4;
-    float acc[4][9];
+    __shared__ __align__(16) bf16 sa[3][C][WGP];  // activation rows, slot = row mod 3
+    __shared__ __align__(16) bf16 sd[3][C][WGP];  // sd[c][co][px] = dz[i][j0 + px - (c - 1)][co]
+    const int lane = threadIdx.x;
+    const int n = lane & 31, kg = lane >> 5;
+    const int strips = (W + 63) / 64, groups = (H + WG_ROWS - 1) / WG_ROWS;
+    const int units = B * strips * groups;
+    f32x16 acc[9];
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int t = 0; t < 9; ++t) acc[t] = f32x16{};
+
+    // one pixel's 32 channels of row ii of image b (zeros outside the image) into LDS
+    // column pos of the channel-major rows at dst (row stride WGP)
+    auto put = [&](bf16 *dst, const bf16 *src, int b, int ii, int jj, int pos) {
+        uint4 v[4] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0)};
+        if (ii >= 0 && ii < H && jj >= 0 && jj < W) {
+            const uint4 *g = reinterpret_cast<const uint4 *>(src + (((long long)b * H + ii) * W + jj) * C);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) acc[q][t] = 0.0f;
-    for (long long p = p0; p < p1; ++p) {
-        const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
-        float g[4];
+            for (int q = 0; q < 4; ++q) v[q] = g[q];
+        }
+        const unsigned short *h = reinterpret_cast<const unsigned short *>(v);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) g[q] = bfv(dz[p * C + cq + q]);
+        for (int ch = 0; ch < C; ++ch) dst[ch * WGP + pos] = bf16{h[ch]};
+    };
+
+    for (int u = blockIdx.x; u < units; u += gridDim.x) {
+        const int strip = u % strips, g = (u / strips) % groups, b = u / (strips * groups);
+        const int j0 = strip * 64, i0 = g * WG_ROWS, i1 = min(i0 + WG_ROWS, H);
+        __syncthreads();  // the previous unit's reads are done
+        put(&sa[(i0 - 1 + 3) % 3][0][0], act, b, i0 - 1, j0 + lane, lane);
+        put(&sa[i0 % 3][0][0], act, b, i0, j0 + lane, lane);
+        for (int i = i0; i < i1; ++i) {
+            __syncthreads();  // the previous row's reads are done
+            put(&sa[(i + 1) % 3][0][0], act, b, i + 1, j0 + lane, lane);
+            // dz row i: this lane's pixel j0 + lane goes to column lane + (c - 1) of copy c
+            {
+                uint4 v[4] = {make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0), make_uint4(0, 0, 0, 0),
+                              make_uint4(0, 0, 0, 0)};
+                const int jj = j0 + lane;
+                if (jj < W) {
+                    const uint4 *gp = reinterpret_cast<const uint4 *>(dz + (((long long)b * H + i) * W + jj) * C);
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
-            const float a = (ii >= 0 && ii < H && jj >= 0 && jj < W)
-                                ? bfv(act[(((long long)b * H + ii) * W + jj) * C + ci]) : 0.0f;
+                    for (int q = 0; q < 4; ++q) v[q] = gp[q];
+                }
+                const unsigned short *h = reinterpret_cast<const unsigned short *>(v);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[q][t] += g[q] * a;
+                for (int ch = 0; ch < C; ++ch) {
+                    if (lane >= 1) sd[0][ch][lane - 1] = bf16{h[ch]};
+                    sd[1][ch][lane] = bf16{h[ch]};
+                    if (lane <= 62) sd[2][ch][lane + 1] = bf16{h[ch]};
+                }
+            }
+            // the two pixels beyond the strip: j0 + 64 -> copy 0 column 63, j0 - 1 -> copy 2 column 0
+            if (lane == 0) put(&sd[2][0][0], dz, b, i, j0 - 1, 0);
+            if (lane == 63) put(&sd[0][0][0], dz, b, i, j0 + 64, 63);
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const int slot = (i + a - 1 + 3) % 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                    for (int kc = 0; kc < 4; ++kc) {
+                        const int px0 = 16 * kc + 8 * kg;
+                        bf16x8 av, bv;
+                        __builtin_memcpy(&av, &sd[c][n][px0], 16);
+                        __builtin_memcpy(&bv, &sa[slot][n][px0], 16);
+                        acc[3 * a + c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[3 * a + c], 0, 0, 0);
+                    }
+                }
+            }
         }
     }
+    // accumulator register r of tap t: co = 8 (r / 4) + 4 kg + r % 4, ci = n
     float *dst = part + (size_t)blockIdx.x * NW2;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-        for (int t = 0; t < 9; ++t) dst[((cq + q) * C + ci) * 9 + t] = acc[q][t];
+        for (int r = 0; r < 16; ++r) dst[((8 * (r / 4) + 4 * kg + r % 4) * C + n) * 9 + t] = acc[t][r];
 }
 
-// Weight gradient of layer 1: part[blk][co*9 + t] = sum dz1[p][co] * a0[p + off_t]
-// (a0 = BF16 of x * scale, as the forward pass used).
-__global__ __launch_bounds__(NW1) void wgrad1_kernel(const float *__restrict__ x, int ldx, const bf16 *__restrict__ dz1,
-                                                     float *__restrict__ part, int B, int H, int W)
+// Weight gradients of the thin layers, split over WG_BLOCKS pixel ranges; thread (channel,
+// tap) sums over its block's range row by row (no division per pixel), four interleaved
+// partial sums for instruction-level parallelism, combined in a fixed order.
+//   layer 1: part[blk][co*9 + t] = sum dz1[p][co] * a0[p + off_t]  (a0 = BF16 of x, as the
+//            forward pass used)
+//   layer 4: part[blk][ci*9 + t] = sum dy[p] * a3[p + off_t][ci]
+template <bool L4>
+__global__ __launch_bounds__(NW1) void wgrad_thin_kernel(const float *__restrict__ x, int ldx,
+                                                         const bf16 *__restrict__ a3, const float *__restrict__ dy,
+                                                         const bf16 *__restrict__ dz1, float *__restrict__ part,
+                                                         int B, int H, int W)
 {
+    static_assert(NW1 == NW4, "one block shape for both thin layers");
     const long long N = (long long)B * H * W;
     const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
-    const int co = threadIdx.x / 9, t = threadIdx.x % 9;
-    float acc = 0.0f;
-    for (long long p = p0; p < p1; ++p) {
-        const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
-        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
-        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
-        const float a0 = bf16_to_f32(f32_to_bf16_rne(x[((long long)b * H + ii) * ldx + jj]));
-        acc += bfv(dz1[p * C + co]) * a0;
+    const int ch = threadIdx.x / 9, t = threadIdx.x % 9;
+    const int dyo = tap_dy(t, false), dxo = tap_dx(t, false);
+    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    long long p = p0;
+    long long row = p0 / W;  // b * H + i
+    int j = (int)(p0 - row * W);
+    while (p < p1) {
+        const int i = (int)(row % H);
+        const long long b = row / H;
+        const int jend = (int)min((long long)W, (long long)j + (p1 - p));
+        const int ii = i + dyo;
+        const bool rowok = ii >= 0 && ii < H;
+        const long long srow = (b * H + (rowok ? ii : 0));  // source row (used only if rowok)
+        auto term = [&](int jj) -> float {
+            const int c = jj + dxo;
+            const bool ok = rowok && c >= 0 && c < W;
+            if (L4) {
+                const float s = ok ? bfv(a3[(srow * W + c) * C + ch]) : 0.0f;
+                return dy[row * W + jj] * s;
+            } else {
+                const float a0 = ok ? bf16_to_f32(f32_to_bf16_rne(x[srow * ldx + c])) : 0.0f;
+                return bfv(dz1[(row * W + jj) * C + ch]) * a0;
+            }
+        };
+        int jj = j;
+        for (; jj + 4 <= jend; jj += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc[u] += term(jj + u);
+        }
+        for (; jj < jend; ++jj) acc[0] += term(jj);
+        p += jend - j;
+        j = 0;
+        row += 1;
     }
-    part[(size_t)blockIdx.x * NW1 + threadIdx.x] = acc;
-}
-
-// Weight gradient of layer 4: part[blk][ci*9 + t] = sum dy[p] * a3[p + off_t][ci].
-__global__ __launch_bounds__(NW4) void wgrad4_kernel(const bf16 *__restrict__ a3, const float *__restrict__ dy,
-                                                     float *__restrict__ part, int B, int H, int W)
-{
-    const long long N = (long long)B * H * W;
-    const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
-    const int ci = threadIdx.x / 9, t = threadIdx.x % 9;
-    float acc = 0.0f;
-    for (long long p = p0; p < p1; ++p) {
-        const int j = (int)(p % W), i = (int)((p / W) % H), b = (int)(p / ((long long)W * H));
-        const int ii = i + tap_dy(t, false), jj = j + tap_dx(t, false);
-        if (ii < 0 || ii >= H || jj < 0 || jj >= W) continue;
-        acc += dy[p] * bfv(a3[(((long long)b * H + ii) * W + jj) * C + ci]);
-    }
-    part[(size_t)blockIdx.x * NW4 + threadIdx.x] = acc;
+    part[(size_t)blockIdx.x * NW1 + threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // g[off + q] = sum over blocks (in block order) of part[blk][q].
@@ -686,7 +766,7 @@ hipError_t net_alloc(NetState &s)
     s.nw.w3f = s.nw.w2b + NW2;
     s.nw.w3b = s.nw.w3f + NW2;
     s.nw.w4 = s.nw.w3b + NW2;
-    return hipMalloc(&s.part, sizeof(float) * (size_t)WG_BLOCKS * NW2);
+    return hipMalloc(&s.part, sizeof(float) * (size_t)std::max(WG_BLOCKS, WGM_BLOCKS) * NW2);
 }
 
 hipError_t net_set(NetState &s, const float *host)
@@ -770,23 +850,27 @@ hipError_t net_gradient(NetState &s, const float *x, const float *t, int B, int 
         hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(BX), 0, st, s.dpart, (int)blocks_for(N), loss_out,
                            1.0 / (double)N);
     const unsigned cb = conv_blocks(B, H, W);
+    const unsigned wgm = (unsigned)std::min<long long>(
+        (long long)B * ((W + 63) / 64) * ((H + WG_ROWS - 1) / WG_ROWS), WGM_BLOCKS);
     // layer 4
-    hipLaunchKernelGGL(wgrad4_kernel, dim3(WG_BLOCKS), dim3(NW4), 0, st, s.a3, s.dy, s.part, B, H, W);
+    hipLaunchKernelGGL(wgrad_thin_kernel<true>, dim3(WG_BLOCKS), dim3(NW4), 0, st, (const float *)nullptr, 0, s.a3,
+                       s.dy, (const bf16 *)nullptr, s.part, B, H, W);
     hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW4)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW4,
                        s.g + OFF4);
     hipLaunchKernelGGL(l4_bwd_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.dy, s.nw.w4, s.a3, s.dz3, B, H, W);
     // layer 3
-    hipLaunchKernelGGL(wgrad32_kernel, dim3(WG_BLOCKS), dim3(BX), 0, st, s.a2, s.dz3, s.part, B, H, W);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW2,
+    hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3(wgm), dim3(64), 0, st, s.a2, s.dz3, s.part, B, H, W);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, (int)wgm, NW2,
                        s.g + OFF3);
     hipLaunchKernelGGL(conv32_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz3, s.nw.w3b, s.dz2, s.a2, B, H, W);
     // layer 2
-    hipLaunchKernelGGL(wgrad32_kernel, dim3(WG_BLOCKS), dim3(BX), 0, st, s.a1, s.dz2, s.part, B, H, W);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW2,
+    hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3(wgm), dim3(64), 0, st, s.a1, s.dz2, s.part, B, H, W);
+    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, (int)wgm, NW2,
                        s.g + OFF2);
     hipLaunchKernelGGL(conv32_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz2, s.nw.w2b, s.dz1, s.a1, B, H, W);
     // layer 1
-    hipLaunchKernelGGL(wgrad1_kernel, dim3(WG_BLOCKS), dim3(NW1), 0, st, x, W, s.dz1, s.part, B, H, W);
+    hipLaunchKernelGGL(wgrad_thin_kernel<false>, dim3(WG_BLOCKS), dim3(NW1), 0, st, x, W, (const bf16 *)nullptr,
+                       (const float *)nullptr, s.dz1, s.part, B, H, W);
     hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW1)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW1, s.g);
     return hipGetLastError();
 }

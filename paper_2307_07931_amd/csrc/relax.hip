@@ -21,13 +21,14 @@ int relax_default_rows(int dtype, int n, int sweeps)
         rows = sweeps <= 4 ? 16 : 32;
     else
         rows = (sweeps == 3 || sweeps == 4) ? 16 : 32;
+    // small grids are latency-bound: keep at least about 16 bands so more waves run at once
+    rows = std::min(rows, std::max(8, (n + 2) / 16));
     if ((sweeps + 1) % 3 == 0) {
         const int u = sweeps + 1;
         rows -= (rows + 2 * sweeps) % u;  // largest such height not above the heuristic
         if (rows < 8) rows += u;
     }
-    const int cap = std::max(8, (n + 2) / 8);
-    return std::min(rows, cap);
+    return rows;
 }
 
 int relax_num_waves(int dtype, int n, int sweeps, int resmode, int rows)
