@@ -40,16 +40,16 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # HBM traffic of the FP64 fused relaxation at 4096^2, per launch: rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE (KiB per dispatch, averaged over the dispatches of a short bench run with
 # the given sweeps per launch and tile rows), scaled by what the same counters read for a
-# 1 GiB device-to-device copy (FETCH_SIZE 524302.76 KiB -> x 1048576 / 524302.76,
+# 1 GiB device-to-device copy (FETCH_SIZE 524302.64 KiB -> x 1048576 / 524302.64,
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
-TRAFFIC_SHA256 = "0fe94db4060853a24ca851a2dd121cd3c05fa7bdbe99c9ffb939b9f80ce13309"
-TRAFFIC_SCALE = (1048576.0 / 524302.76, 1.0)
+TRAFFIC_SHA256 = "dd117e7d6df74a0bfb4e05eaa1e0447a06861afd3be5640b9f17d7edd4a8ff14"
+TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 20): (236779.65, 131282.43), (8, 24): (247089.08, 131279.99), (8, 28): (218492.70, 131277.75),
-    (8, 29): (211965.86, 131277.99), (8, 32): (223959.30, 131278.37), (8, 38): (192628.13, 131275.83),
-    (1, 16): (167084.32, 132516.75),
+    (8, 20): (237776.38, 131282.25), (8, 24): (247284.75, 131279.28), (8, 28): (218591.65, 131278.79),
+    (8, 29): (212129.62, 131277.91), (8, 32): (224314.06, 131277.99), (8, 38): (192723.78, 131276.15),
+    (1, 12): (177191.25, 131275.39), (1, 16): (166649.10, 131277.71),
 }
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
