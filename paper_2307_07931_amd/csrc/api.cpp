@@ -604,8 +604,9 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
             BatchProblem bp{phi, f, n, ld, ld_f, h, lambda};
             BatchStat bs;
             char err[256] = "";
-            st = batch_solve(*ctx->batch, lowp, &bp, 1, bc, o->rtol, o->norm, o->max_sweeps, inner,
-                             std::min(k_in, inner), 8, &bs, s, err, sizeof err);
+            const int ks = std::min(k_in, inner);
+            st = batch_solve(*ctx->batch, lowp, &bp, 1, bc, o->rtol, o->norm, o->max_sweeps, inner, ks, 8,
+                             pick_rows(ctx, lowp, n, ldl, ks), &bs, s, err, sizeof err);
             // a problem that did not converge is reported through bs.state below
             if (st != PX_OK && st != PX_ENOTCONV && st != PX_ENONFINITE && st != PX_EDIVERGED)
                 return fail(st, "%s", err);
@@ -774,6 +775,7 @@ int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *o,
     const int tk = ctx->batch->tuned_k[lowp];
     const int k = std::min(o->tblock ? o->tblock : (tk ? tk : 8), inner);
     st = batch_solve(*ctx->batch, lowp, bp.data(), nprob, o->bc, o->rtol, o->norm, o->max_sweeps, inner, k, 8,
+                     ctx->tile_rows,
                      bs.data(), (hipStream_t)stream, err, sizeof err);
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (stats)

@@ -528,8 +528,8 @@ int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob
 // ------------------------------------------------------------------ solve
 
 int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, int bc, double rtol,
-                int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, BatchStat *stats,
-                hipStream_t user_stream, char *err, size_t errlen)
+                int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, int forced_rows,
+                BatchStat *stats, hipStream_t user_stream, char *err, size_t errlen)
 {
     const size_t les = (size_t)elem_size(lowp);
     const int L = (inner + k - 1) / k;
@@ -634,7 +634,7 @@ int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, in
         r.bc = bc;
         r.c = 1.0 / (q.h * q.h);
         for (auto &sh : shapes) {
-            const int rows = w.rows_for(lowp, q.n, sh.k, 0);
+            const int rows = w.rows_for(lowp, q.n, sh.k, forced_rows);
             sh.a[0][p] = make_kargs(lowp, base + da[p], base + db[p], base + rl[p], q.n, ldl[p], ldl[p], q.h,
                                     q.lambda, bc, sh.k, RES_NONE, rows);
             sh.a[1][p] = make_kargs(lowp, base + db[p], base + da[p], base + rl[p], q.n, ldl[p], ldl[p], q.h,

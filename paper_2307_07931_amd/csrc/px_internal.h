@@ -136,8 +136,8 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
 int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int bc, hipStream_t s,
                    int *best_k, char *err, size_t errlen);
 int batch_solve(BatchWork &w, int lowp, const BatchProblem *probs, int nprob, int bc, double rtol,
-                int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, BatchStat *stats,
-                hipStream_t user_stream, char *err, size_t errlen);
+                int use_l2, long long max_sweeps, int inner, int k, int steps_per_graph, int forced_rows,
+                BatchStat *stats, hipStream_t user_stream, char *err, size_t errlen);
 
 // ---- learned correction (net.hip)
 // Records the message of a failing ABI call (px_last_error) and returns code.
