@@ -98,8 +98,10 @@ int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
 
 /*
  * Autotuner: times the fused relaxation on the caller's buffers for every
- * sweeps-per-launch k in 1..8 and a list of tile heights, and remembers the
- * fastest (k, rows) in ctx for this (dtype, n, ld).  Later calls with
+ * sweeps-per-launch k in 1..8 and a list of tile heights (fastest of five
+ * single launches each), re-times the four best as runs of 8 back-to-back
+ * launches, and remembers the fastest (k, rows) of that second pass in ctx
+ * for this (dtype, n, ld).  Later calls with
  * tblock == 0 on such a grid use it (explicit tblock or px_ctx_set_tile_rows
  * override it).  phi_in is only read; phi_out is overwritten with scratch
  * iterates; f as in px_relax_fused.  Waits on `stream`.  best_k, best_rows and

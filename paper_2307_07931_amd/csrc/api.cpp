@@ -443,8 +443,12 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
     hipEvent_t e0, e1;
     PX_HIP(hipEventCreate(&e0), "hipEventCreate");
     PX_HIP(hipEventCreate(&e1), "hipEventCreate");
-    int bk = 0, br = 0;
-    double bg = 0.0;
+    // first pass: every candidate, fastest of five single launches; the TOP best go on
+    // to a second pass of back-to-back launches (the way a sweep loop runs them), which
+    // separates candidates that single launches rank within their noise
+    constexpr int TOP = 4;
+    struct Cand { double g; int k, rows; };
+    Cand top[TOP] = {};
     int err = PX_OK;
     for (int k = 1; k <= 8 && !err; ++k) {
         for (int rows : ROWS) {
@@ -473,16 +477,45 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
             }
             if (err) break;
             const double g = ms > 0.f ? k * (double)n * n / (ms * 1e-3) / 1e9 : 0.0;
-            if (g > bg) {
-                bg = g;
-                bk = k;
-                br = rows;
+            for (int i = 0; i < TOP; ++i) {
+                if (g > top[i].g) {
+                    for (int j = TOP - 1; j > i; --j) top[j] = top[j - 1];
+                    top[i] = Cand{g, k, rows};
+                    break;
+                }
             }
+        }
+    }
+    constexpr int RUN = 8, ROUNDS = 3;
+    double g2[TOP] = {};
+    for (int round = 0; round < ROUNDS && !err; ++round) {
+        for (int i = 0; i < TOP && !err; ++i) {
+            if (top[i].k == 0) continue;
+            hipError_t he = hipEventRecord(e0, s);
+            for (int l = 0; l < RUN && !err && he == hipSuccess; ++l)
+                err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, top[i].k,
+                                 top[i].k, bc, RES_NONE, nullptr, s, top[i].rows);
+            if (err) break;
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess) {
+                err = hip_fail(he, "autotune timing");
+                break;
+            }
+            const double g = ms > 0.f ? RUN * top[i].k * (double)n * n / (ms * 1e-3) / 1e9 : 0.0;
+            g2[i] = std::max(g2[i], g);
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err) return err;
+    int bi = 0;
+    for (int i = 1; i < TOP; ++i)
+        if (g2[i] > g2[bi]) bi = i;
+    const int bk = top[bi].k, br = top[bi].rows;
+    const double bg = g2[bi];
     px_tuned &t = ctx->tuned[dtype];
     t.n = n;
     t.ld = ld;

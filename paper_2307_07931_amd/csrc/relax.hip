@@ -63,6 +63,10 @@ hipError_t relax_launch(int dtype, const RelaxLaunch &a, hipStream_t s)
     // vector loads/stores need every row start aligned to V elements
     const bool vec = aligned(a.in, V * es) && aligned(a.out, V * es) && a.ld % V == 0 &&
                      aligned(a.f, V * es) && a.ld_f % V == 0;
+    // stream the output past the caches when phi, phi' and f together exceed the
+    // 256 MB Infinity Cache
+    const size_t ws = (2 * (size_t)(a.n + 2) * (size_t)a.ld + (size_t)a.n * (size_t)a.ld_f) * es;
+    ka.nt_store = ws > ((size_t)256 << 20) ? 1 : 0;
     ka.pmax = a.part.max_bits;
     ka.psum = a.part.sum;
     LaunchFn fn = nullptr;

@@ -78,6 +78,7 @@ struct KArgs {
     int n, ld, ld_f, bc;
     double c, w, lam;
     int halo, col_origin, stride, tiles_x, rows, ntiles;
+    int nt_store;  // non-temporal row stores (working set larger than the Infinity Cache)
     unsigned long long *pmax;
     double *psum;
 };
@@ -114,6 +115,10 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int RSRC_WORD3 = 0x00020000;  // raw (untyped) buffer, gfx9-family data format
 constexpr int OOB = (int)0x80000000u;    // beyond every row descriptor (rows < 2 GiB)
+// cache policy of a store: non-temporal (streamed past the caches).  Worth it when the
+// grids of a launch do not fit the 256 MB Infinity Cache: each new row would otherwise
+// push out input rows that other waves are about to read.
+constexpr int CPOL_NT = 2;
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int row, int nrows,
                                                            int row_bytes)
@@ -141,14 +146,18 @@ template <int V> struct Io<double, V, true> {
         d[0] = __hiloint2double((int)x.u.y, (int)x.u.x);
         d[1] = __hiloint2double((int)x.u.w, (int)x.u.z);
     }
-    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V])
+    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V], bool nt)
     {
         u32x4 u;
         u.x = (unsigned)__double2loint(d[0]);
         u.y = (unsigned)__double2hiint(d[0]);
         u.z = (unsigned)__double2loint(d[1]);
         u.w = (unsigned)__double2hiint(d[1]);
-        __builtin_amdgcn_raw_buffer_store_b128(u, r, off_elems == OOB ? OOB : off_elems * 8, 0, 0);
+        const int off = off_elems == OOB ? OOB : off_elems * 8;
+        if (nt)
+            __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, CPOL_NT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, 0);
     }
 };
 template <int V> struct Io<double, V, false> {
@@ -182,14 +191,18 @@ template <int V> struct Io<float, V, true> {
         d[2] = __uint_as_float(x.u.z);
         d[3] = __uint_as_float(x.u.w);
     }
-    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V])
+    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V], bool nt)
     {
         u32x4 u;
         u.x = __float_as_uint(d[0]);
         u.y = __float_as_uint(d[1]);
         u.z = __float_as_uint(d[2]);
         u.w = __float_as_uint(d[3]);
-        __builtin_amdgcn_raw_buffer_store_b128(u, r, off_elems == OOB ? OOB : off_elems * 4, 0, 0);
+        const int off = off_elems == OOB ? OOB : off_elems * 4;
+        if (nt)
+            __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, CPOL_NT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b128(u, r, off, 0, 0);
     }
 };
 template <int V> struct Io<float, V, false> {
@@ -223,12 +236,16 @@ template <int V> struct Io<bf16, V, true> {
         d[2] = __uint_as_float(x.u.y << 16);
         d[3] = __uint_as_float(x.u.y & 0xffff0000u);
     }
-    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V])
+    __device__ static void store(__amdgpu_buffer_rsrc_t r, int off_elems, const A (&d)[V], bool nt)
     {
         u32x2 u;
         u.x = (unsigned)f32_to_bf16_rne(d[0]) | ((unsigned)f32_to_bf16_rne(d[1]) << 16);
         u.y = (unsigned)f32_to_bf16_rne(d[2]) | ((unsigned)f32_to_bf16_rne(d[3]) << 16);
-        __builtin_amdgcn_raw_buffer_store_b64(u, r, off_elems == OOB ? OOB : off_elems * 2, 0, 0);
+        const int off = off_elems == OOB ? OOB : off_elems * 2;
+        if (nt)
+            __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, CPOL_NT);
+        else
+            __builtin_amdgcn_raw_buffer_store_b64(u, r, off, 0, 0);
     }
 };
 template <int V> struct Io<bf16, V, false> {
@@ -303,7 +320,8 @@ template <> struct Store1<bf16> {
 // vectors (`whole`, wave-uniform), element by element otherwise.
 template <typename T, int V, bool VEC>
 __device__ __forceinline__ void store_cols(__amdgpu_buffer_rsrc_t r, int col0, int lo, int hi,
-                                           bool whole, const typename Elem<T>::A (&val)[V], bool negate)
+                                           bool whole, const typename Elem<T>::A (&val)[V], bool negate,
+                                           bool nt = false)
 {
     using A = typename Elem<T>::A;
     A x[V];
@@ -311,7 +329,7 @@ __device__ __forceinline__ void store_cols(__amdgpu_buffer_rsrc_t r, int col0, i
     for (int v = 0; v < V; ++v) x[v] = negate ? -val[v] : val[v];
     if constexpr (VEC) {
         if (whole) {
-            Io<T, V, true>::store(r, (col0 >= lo && col0 + V <= hi) ? col0 : OOB, x);
+            Io<T, V, true>::store(r, (col0 >= lo && col0 + V <= hi) ? col0 : OOB, x, nt);
             return;
         }
     }
@@ -485,7 +503,7 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                         if constexpr (!EDGE) {
                             // interior tile: interior rows and columns only, whole vectors
                             store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv,
-                                                  false);
+                                                  false, p.nt_store != 0);
                         } else if (dir) {
                             if (row_in) {
                                 const auto ro = row_rsrc(p.out, r, n + 2, rb);
@@ -538,11 +556,82 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 
 // Interior tiles of launches without norms whose K + 1 is a multiple of 3 (K = 2, 5, 8):
 // the step loop is unrolled U = K + 1 times, so the 3-row windows of every level (3 | U),
-// the (K + 1)-row ring of f (U rows) and a 3-deep ring of prefetched rows all rotate by
-// renaming: row x of a level lives in slot (x - sb) mod 3, f of phi row x in slot
-// (x - sb) mod U.  The arithmetic and its order are those of run_tile; only where values
-// are kept differs.  The step count is rounded up to a multiple of U (the extra steps
-// compute rows past the band and store nothing).
+// the (K + 1)-row ring of lambda f (U rows) and a 3-deep ring of prefetched rows all rotate
+// by renaming: row x of a level lives in slot (x - sb) mod 3, lambda f of phi row x in slot
+// (x - sb) mod U.  The product lambda f is formed once per row when the row arrives and
+// reused by all K levels: the same rounded product each level would form, so the results
+// are those of run_tile bit for bit.  Level t starts 2t steps after the first row; the
+// first blocks of U steps (the pipeline filling up) test which levels are active, the
+// rest run every level unconditionally.  The step count is rounded up to a multiple of U
+// (the extra steps compute rows past the band and store nothing).
+template <typename T, int V, int K, bool VEC, bool FILLING>
+__device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, int s0, int sb,
+                                              typename Elem<T>::A (&win)[K][3][V],
+                                              typename Elem<T>::A (&lf)[K + 1][V],
+                                              typename Io<T, V, VEC>::Raw (&pf)[3],
+                                              typename Io<T, V, VEC>::Raw (&pff)[3])
+{
+    using E = Elem<T>;
+    using A = typename E::A;
+    using IO = Io<T, V, VEC>;
+    constexpr int U = K + 1;
+    constexpr int PR = 3;
+    constexpr int ES = (int)sizeof(T);
+    constexpr int M3 = 3 * U;  // keeps the slot arithmetic non-negative
+    const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y1 = tl.y1;
+    const int rb = p.ld * ES, rbf = p.ld_f * ES;
+    const A w = (A)p.w, lam = (A)p.lam;
+    const int fc = VEC ? mc : mc - 1;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        const int s = s0 + q;
+        IO::unpack(pf[q % PR], win[0][q % 3]);
+        {
+            A fo[V], fv[V];
+            IO::unpack(pff[q % PR], fo);
+            if constexpr (VEC) {
+                fv[0] = lane_from_left(fo[V - 1]);
+#pragma unroll
+                for (int v = 1; v < V; ++v) fv[v] = fo[v - 1];
+            } else {
+#pragma unroll
+                for (int v = 0; v < V; ++v) fv[v] = fo[v];
+            }
+#pragma unroll
+            for (int v = 0; v < V; ++v) lf[q][v] = lam * fv[v];
+        }
+        pf[q % PR] = IO::load(row_rsrc(p.in, s + PR, n + 2, rb), mc);
+        pff[q % PR] = IO::load(row_rsrc(p.f, s + PR - 1, n, rbf), fc);
+#pragma unroll
+        for (int t = 1; t <= K; ++t) {
+            if (FILLING && s < sb + 2 * t) break;  // rows this level does not need yet
+            const int r = s - t;
+            const int sn = (q - t - 1 + M3) % 3, sc = (q - t + M3) % 3, ss = (q - t + 1 + M3) % 3;
+            const int sf = (q - t + U) % U;
+            const A left = lane_from_left(win[t - 1][sc][V - 1]);
+            const A right = lane_from_right(win[t - 1][sc][0]);
+            A nv[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const A C = win[t - 1][sc][v];
+                const A N = win[t - 1][sn][v];
+                const A S = win[t - 1][ss][v];
+                const A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
+                const A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
+                const A st = (((N - (A)4 * C) + Wn) + En) + S;
+                nv[v] = E::round((C + w * st) - lf[sf][v]);
+            }
+            if (t < K) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
+            } else if (r < y1) {  // r >= y0 once level K runs
+                store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv, false,
+                                      p.nt_store != 0);
+            }
+        }
+    }
+}
+
 template <typename T, int V, int K, bool VEC>
 __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
 {
@@ -554,12 +643,11 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
     constexpr int PR = 3;
     static_assert(U % 3 == 0, "window slots must repeat within the unrolled steps");
     constexpr int ES = (int)sizeof(T);
-    const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
+    const int n = tl.n, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
-    const A w = (A)p.w, lam = (A)p.lam;
 
     A win[K][3][V];
-    A fr[U][V];
+    A lf[U][V];
 #pragma unroll
     for (int t = 0; t < K; ++t)
 #pragma unroll
@@ -569,7 +657,7 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
 #pragma unroll
     for (int j = 0; j < U; ++j)
 #pragma unroll
-        for (int v = 0; v < V; ++v) fr[j][v] = 0;
+        for (int v = 0; v < V; ++v) lf[j][v] = 0;
     const int fc = VEC ? mc : mc - 1;
     const int sb = y0 - K, se = sb + (y1 - y0 + 2 * K + U - 1) / U * U;
     Raw pf[PR], pff[PR];
@@ -578,54 +666,9 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
         pf[q] = IO::load(row_rsrc(p.in, sb + q, n + 2, rb), mc);
         pff[q] = IO::load(row_rsrc(p.f, sb + q - 1, n, rbf), fc);
     }
-    for (int s0 = sb; s0 < se; s0 += U) {
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            const int s = s0 + q;
-            IO::unpack(pf[q % PR], win[0][q % 3]);
-            {
-                A fo[V];
-                IO::unpack(pff[q % PR], fo);
-                if constexpr (VEC) {
-                    fr[q][0] = lane_from_left(fo[V - 1]);
-#pragma unroll
-                    for (int v = 1; v < V; ++v) fr[q][v] = fo[v - 1];
-                } else {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) fr[q][v] = fo[v];
-                }
-            }
-            pf[q % PR] = IO::load(row_rsrc(p.in, s + PR, n + 2, rb), mc);
-            pff[q % PR] = IO::load(row_rsrc(p.f, s + PR - 1, n, rbf), fc);
-#pragma unroll
-            for (int t = 1; t <= K; ++t) {
-                if (s < y0 - K + 2 * t) break;  // rows this level does not need yet
-                const int r = s - t;
-                constexpr int M3 = 3 * U;  // keeps the slot arithmetic non-negative
-                const int sn = (q - t - 1 + M3) % 3, sc = (q - t + M3) % 3, ss = (q - t + 1 + M3) % 3;
-                const int sf = (q - t + U) % U;
-                const A left = lane_from_left(win[t - 1][sc][V - 1]);
-                const A right = lane_from_right(win[t - 1][sc][0]);
-                A nv[V];
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    const A C = win[t - 1][sc][v];
-                    const A N = win[t - 1][sn][v];
-                    const A S = win[t - 1][ss][v];
-                    const A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
-                    const A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
-                    const A st = (((N - (A)4 * C) + Wn) + En) + S;
-                    nv[v] = E::round((C + w * st) - lam * fr[sf][v]);
-                }
-                if (t < K) {
-#pragma unroll
-                    for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
-                } else if (r >= y0 && r < y1) {
-                    store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv, false);
-                }
-            }
-        }
-    }
+    int s0 = sb;
+    for (; s0 < se && s0 < sb + 2 * K; s0 += U) renamed_block<T, V, K, VEC, true>(p, tl, s0, sb, win, lf, pf, pff);
+    for (; s0 < se; s0 += U) renamed_block<T, V, K, VEC, false>(p, tl, s0, sb, win, lf, pf, pff);
 }
 
 // One wave tile of one problem: geometry, interior/edge dispatch, streaming loop.

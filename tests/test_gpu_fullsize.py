@@ -58,3 +58,30 @@ def test_fullsize_sampled_windows_and_norms(ctx, dt):
     gi = np.ascontiguousarray(g[:, :n + 2])
     _, mx, sq = oracle.residual(gi, H.oracle_input(f, dt), n, h)
     H.assert_norms(norms, mx, sq, n=n)
+
+
+@pytest.mark.parametrize("tblock", [1, 5, 8])
+def test_fullsize_streamed_stores_short_runs(ctx, tblock):
+    """At 4096^2 FP64 phi, phi' and f exceed the 256 MB Infinity Cache, so the kernel
+    streams its row stores past the caches; a cache policy must not change a value.
+    A random phi0 and 2 launches of `tblock` sweeps (k = 1 takes the halo-free strips,
+    k = 5 and 8 the unrolled interior loop), checked on light-cone windows."""
+    n = N
+    S = 2 * tblock
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    f = W.uniform_rhs(n, W.SEED_UNIFORM_4096)
+    phi0 = np.zeros((n + 2, n + 2))
+    phi0[1:n + 1, 1:n + 1] = W.uniform_rhs(n, 11)
+    print(f"case: full size f64 n={n} sweeps={S} tblock={tblock} random phi0", flush=True)
+    g, norms = H.gpu_relax(phi0, f, n, h, lam, S, "f64", ctx, tblock=tblock)
+    Wn = 2 * S + 64
+    starts = (1, 129, (n - Wn) // 2, n - Wn + 1)
+    compared = 0
+    for r0 in starts:
+        for c0 in starts:
+            compared += H.window_check(g, phi0, f, n, h, lam, S, r0, c0, Wn, "f64")
+    assert compared > 16 * 60 * 60
+    gi = np.ascontiguousarray(g[:, :n + 2])
+    _, mx, sq = oracle.residual(gi, H.oracle_input(f, "f64"), n, h)
+    H.assert_norms(norms, mx, sq, n=n)
