@@ -37,6 +37,37 @@ int relax_num_waves(int dtype, int n, int sweeps, int resmode, int rows)
     return make_geometry(vec_of(dtype), n, NL, rows).ntiles;
 }
 
+// Edge-first launch order (see launch_tile): the interior tiles, by the predicate
+// relax_one_tile uses, form the rectangle [txl, txr) x [tyt, tyb).
+static void set_launch_order(KArgs &ka, const Geometry &g, int V, int n, int NL, int nblocks)
+{
+    int txl = -1, txr = -1, tyt = -1, tyb = -1;
+    for (int tx = 0; tx < g.tiles_x; ++tx) {
+        const int c0 = g.col_origin + tx * g.stride - g.halo;
+        if (c0 >= 1 && c0 + WAVE * V - 1 <= n) {
+            if (txl < 0) txl = tx;
+            txr = tx + 1;
+        }
+    }
+    for (int ty = 0; ty < g.tiles_y; ++ty) {
+        const int y0 = ty * g.rows, y1 = std::min(y0 + g.rows, n + 2);
+        if (y0 - NL >= 1 && y1 + NL - 1 <= n) {
+            if (tyt < 0) tyt = ty;
+            tyb = ty + 1;
+        }
+    }
+    ka.edge_first = 0;
+    ka.txl = ka.txr = ka.tyt = ka.tyb = ka.lead_blocks = 0;
+    if (txl < 0 || tyt < 0) return;  // no interior tile: plain order
+    const int nedge = g.ntiles - (txr - txl) * (tyb - tyt);
+    ka.edge_first = 1;
+    ka.txl = txl;
+    ka.txr = txr;
+    ka.tyt = tyt;
+    ka.tyb = tyb;
+    ka.lead_blocks = std::min(nblocks, ((nedge + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK + 7) / 8 * 8);
+}
+
 hipError_t relax_launch(int dtype, const RelaxLaunch &a, hipStream_t s)
 {
     const int V = vec_of(dtype);
@@ -77,6 +108,7 @@ hipError_t relax_launch(int dtype, const RelaxLaunch &a, hipStream_t s)
     }
     if (!fn) return hipErrorInvalidValue;
     const int nblocks = (g.ntiles + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+    set_launch_order(ka, g, V, a.n, NL, nblocks);
     fn(ka, nblocks, s);
     return hipGetLastError();
 }

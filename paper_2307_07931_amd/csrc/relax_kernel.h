@@ -79,6 +79,10 @@ struct KArgs {
     double c, w, lam;
     int halo, col_origin, stride, tiles_x, rows, ntiles;
     int nt_store;  // non-temporal row stores (working set larger than the Infinity Cache)
+    // edge-first launch order (0 = plain XCD-contiguous order): interior tiles are those
+    // with txl <= tx < txr and tyt <= ty < tyb; the first lead_blocks blocks (a multiple
+    // of 8) take the edge tiles
+    int edge_first, txl, txr, tyt, tyb, lead_blocks;
     unsigned long long *pmax;
     double *psum;
 };
@@ -554,18 +558,29 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 
 }
 
-// Interior tiles of launches without norms whose K + 1 is a multiple of 3 (K = 2, 5, 8):
+// Tiles of launches without norms whose K + 1 is a multiple of 3 (K = 2, 5, 8) -- interior
+// tiles, and with EDGE the edge tiles of homogeneous-Dirichlet grids, which substitute the
+// odd reflection for the neighbour across each boundary face and write the ghost layer:
 // the step loop is unrolled U = K + 1 times, so the 3-row windows of every level (3 | U),
 // the (K + 1)-row ring of lambda f (U rows) and a 3-deep ring of prefetched rows all rotate
-// by renaming: row x of a level lives in slot (x - sb) mod 3, lambda f of phi row x in slot
-// (x - sb) mod U.  The product lambda f is formed once per row when the row arrives and
-// reused by all K levels: the same rounded product each level would form, so the results
-// are those of run_tile bit for bit.  Level t starts 2t steps after the first row; the
-// first blocks of U steps (the pipeline filling up) test which levels are active, the
-// rest run every level unconditionally.  The step count is rounded up to a multiple of U
-// (the extra steps compute rows past the band and store nothing).
-template <typename T, int V, int K, bool VEC, bool FILLING>
-__device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, int s0, int sb,
+// by renaming: the row of step v of a level lives in slot v mod 3, lambda f of the phi row
+// of step v in slot v mod U.  The product lambda f is formed once per row when the row
+// arrives and reused by all K levels: the same rounded product each level would form, so
+// the results are those of run_tile bit for bit.  Level t starts 2t steps after the first
+// row; the first blocks of U steps (the pipeline filling up) test which levels are active,
+// the rest run every level unconditionally.  The step count is rounded up to a multiple of
+// U (the extra steps compute rows past the band and store nothing).
+//
+// UP streams the band from its bottom row upwards.  The arithmetic is unchanged -- N is
+// still the row above and S the row below, summed in the same order -- only the step that
+// delivers each row differs.  Bands alternate direction, so two neighbouring bands read the
+// 2K rows they share at the same end of their lives (both first or both last) while they
+// run side by side, and the second read of a shared row tends to hit the L2.
+#ifndef PX_ALT_DIR
+#define PX_ALT_DIR 1
+#endif
+template <typename T, int V, int K, bool VEC, bool FILLING, bool UP, bool EDGE>
+__device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, int s0, int base,
                                               typename Elem<T>::A (&win)[K][3][V],
                                               typename Elem<T>::A (&lf)[K + 1][V],
                                               typename Io<T, V, VEC>::Raw (&pf)[3],
@@ -578,13 +593,22 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
     constexpr int PR = 3;
     constexpr int ES = (int)sizeof(T);
     constexpr int M3 = 3 * U;  // keeps the slot arithmetic non-negative
-    const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y1 = tl.y1;
+    constexpr int D = UP ? -1 : 1;  // row step of the stream
+    const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
     const A w = (A)p.w, lam = (A)p.lam;
     const int fc = VEC ? mc : mc - 1;
+    // edge tiles (homogeneous Dirichlet): which of this lane's columns are 1 and n
+    bool west[V], east[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        west[v] = EDGE && mc + v == 1;
+        east[v] = EDGE && mc + v == n;
+    }
 #pragma unroll
     for (int q = 0; q < U; ++q) {
-        const int s = s0 + q;
+        const int s = s0 + q;       // step
+        const int x = base + D * s;  // phi row arriving at this step
         IO::unpack(pf[q % PR], win[0][q % 3]);
         {
             A fo[V], fv[V];
@@ -600,13 +624,14 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
 #pragma unroll
             for (int v = 0; v < V; ++v) lf[q][v] = lam * fv[v];
         }
-        pf[q % PR] = IO::load(row_rsrc(p.in, s + PR, n + 2, rb), mc);
-        pff[q % PR] = IO::load(row_rsrc(p.f, s + PR - 1, n, rbf), fc);
+        pf[q % PR] = IO::load(row_rsrc(p.in, x + D * PR, n + 2, rb), mc);
+        pff[q % PR] = IO::load(row_rsrc(p.f, x + D * PR - 1, n, rbf), fc);
 #pragma unroll
         for (int t = 1; t <= K; ++t) {
-            if (FILLING && s < sb + 2 * t) break;  // rows this level does not need yet
-            const int r = s - t;
-            const int sn = (q - t - 1 + M3) % 3, sc = (q - t + M3) % 3, ss = (q - t + 1 + M3) % 3;
+            if (FILLING && s < 2 * t) break;  // rows this level does not need yet
+            const int r = x - D * t;          // row level t computes
+            const int so = (q - t - 1 + M3) % 3, sc = (q - t + M3) % 3, sw = (q - t + 1 + M3) % 3;
+            const int sn = UP ? sw : so, ss = UP ? so : sw;  // slots of rows r - 1 and r + 1
             const int sf = (q - t + U) % U;
             const A left = lane_from_left(win[t - 1][sc][V - 1]);
             const A right = lane_from_right(win[t - 1][sc][0]);
@@ -614,25 +639,54 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const A C = win[t - 1][sc][v];
-                const A N = win[t - 1][sn][v];
-                const A S = win[t - 1][ss][v];
-                const A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
-                const A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
+                A N = win[t - 1][sn][v];
+                A S = win[t - 1][ss][v];
+                A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
+                A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
+                if constexpr (EDGE) {
+                    // odd reflection across the boundary faces; the values computed in
+                    // ghost and outside cells are never read by an interior cell
+                    N = (r == 1) ? -C : N;
+                    S = (r == n) ? -C : S;
+                    Wn = west[v] ? -C : Wn;
+                    En = east[v] ? -C : En;
+                }
                 const A st = (((N - (A)4 * C) + Wn) + En) + S;
                 nv[v] = E::round((C + w * st) - lf[sf][v]);
             }
             if (t < K) {
 #pragma unroll
                 for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
-            } else if (r < y1) {  // r >= y0 once level K runs
-                store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv, false,
-                                      p.nt_store != 0);
+            } else if (UP ? r >= y0 : r < y1) {  // the other bound holds once level K runs
+                if constexpr (!EDGE) {
+                    store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv, false,
+                                          p.nt_store != 0);
+                } else if (r >= 1 && r <= n) {
+                    // interior columns of the row, the ghosts of columns 1 and n, and the
+                    // ghost rows 0 and n + 1 as the mirrors of rows 1 and n
+                    const int rc0 = max(oc0, 1), rc1 = min(oc1, n + 1);
+                    const auto ro = row_rsrc(p.out, r, n + 2, rb);
+                    store_cols<T, V, VEC>(ro, mc, rc0, rc1, tl.whole, nv, false);
+                    if (!tl.whole) {
+#pragma unroll
+                        for (int v = 0; v < V; ++v) {
+                            const bool mine = mc + v >= rc0 && mc + v < rc1;
+                            Store1<T>::st(ro, 0, mine && west[v], -nv[v]);
+                            Store1<T>::st(ro, n + 1, mine && east[v], -nv[v]);
+                        }
+                    }
+                    if (r == 1)
+                        store_cols<T, V, VEC>(row_rsrc(p.out, 0, n + 2, rb), mc, rc0, rc1, tl.whole, nv, true);
+                    if (r == n)
+                        store_cols<T, V, VEC>(row_rsrc(p.out, n + 1, n + 2, rb), mc, rc0, rc1, tl.whole, nv,
+                                              true);
+                }
             }
         }
     }
 }
 
-template <typename T, int V, int K, bool VEC>
+template <typename T, int V, int K, bool VEC, bool UP, bool EDGE>
 __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
 {
     using E = Elem<T>;
@@ -643,6 +697,7 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
     constexpr int PR = 3;
     static_assert(U % 3 == 0, "window slots must repeat within the unrolled steps");
     constexpr int ES = (int)sizeof(T);
+    constexpr int D = UP ? -1 : 1;
     const int n = tl.n, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
 
@@ -659,16 +714,18 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
 #pragma unroll
         for (int v = 0; v < V; ++v) lf[j][v] = 0;
     const int fc = VEC ? mc : mc - 1;
-    const int sb = y0 - K, se = sb + (y1 - y0 + 2 * K + U - 1) / U * U;
+    const int base = UP ? y1 - 1 + K : y0 - K;  // first row of the stream
+    const int steps = (y1 - y0 + 2 * K + U - 1) / U * U;
     Raw pf[PR], pff[PR];
 #pragma unroll
     for (int q = 0; q < PR; ++q) {
-        pf[q] = IO::load(row_rsrc(p.in, sb + q, n + 2, rb), mc);
-        pff[q] = IO::load(row_rsrc(p.f, sb + q - 1, n, rbf), fc);
+        pf[q] = IO::load(row_rsrc(p.in, base + D * q, n + 2, rb), mc);
+        pff[q] = IO::load(row_rsrc(p.f, base + D * q - 1, n, rbf), fc);
     }
-    int s0 = sb;
-    for (; s0 < se && s0 < sb + 2 * K; s0 += U) renamed_block<T, V, K, VEC, true>(p, tl, s0, sb, win, lf, pf, pff);
-    for (; s0 < se; s0 += U) renamed_block<T, V, K, VEC, false>(p, tl, s0, sb, win, lf, pf, pff);
+    int s0 = 0;
+    for (; s0 < steps && s0 < 2 * K; s0 += U)
+        renamed_block<T, V, K, VEC, true, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff);
+    for (; s0 < steps; s0 += U) renamed_block<T, V, K, VEC, false, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff);
 }
 
 // One wave tile of one problem: geometry, interior/edge dispatch, streaming loop.
@@ -690,8 +747,19 @@ __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lan
     const bool interior = c0 >= 1 && c0 + WAVE * V - 1 <= n && y0 - NL >= 1 && y1 + NL - 1 <= n;
     const Tile tl{n, oc0, oc1, mc, y0, y1, whole};
     if constexpr (RM == RES_NONE && (K + 1) % 3 == 0) {
+        const bool up = PX_ALT_DIR && (ty & 1);
         if (interior) {
-            run_tile_renamed<T, V, K, VEC>(p, tl);
+            if (up)
+                run_tile_renamed<T, V, K, VEC, true, false>(p, tl);
+            else
+                run_tile_renamed<T, V, K, VEC, false, false>(p, tl);
+            return;
+        }
+        if (p.bc == DIRICHLET0) {
+            if (up)
+                run_tile_renamed<T, V, K, VEC, true, true>(p, tl);
+            else
+                run_tile_renamed<T, V, K, VEC, false, true>(p, tl);
             return;
         }
     }
@@ -723,13 +791,56 @@ __device__ __forceinline__ int xcd_block()
     return (b < nb8) ? ((b & 7) * (nb8 >> 3) + (b >> 3)) : b;
 }
 
+// Launch order.  Edge tiles (boundary substitution and ghost writes: longer-lived than
+// interior waves, by a factor up to 2.5 where they take run_tile) go first, spread over all XCDs,
+// so that no slow wave starts near the end of the launch and stretches its tail; the
+// interior tiles follow, each XCD taking a contiguous run.  Returns the tile index
+// (ty * tiles_x + tx), or ntiles for a wave without a tile.
+__device__ __forceinline__ int launch_tile(const KArgs &p, int wave)
+{
+    if (!p.edge_first) return xcd_block() * WAVES_PER_BLOCK + wave;
+    const int nb = gridDim.x, b = blockIdx.x, S = p.lead_blocks;
+    int lb = b;
+    if (b >= S) {  // S is a multiple of 8, so block b still runs on XCD (b - S) mod 8
+        const int j = b - S, m8 = (nb - S) & ~7;
+        lb = S + ((j < m8) ? ((j & 7) * (m8 >> 3) + (j >> 3)) : j);
+    }
+    const int i = lb * WAVES_PER_BLOCK + wave;
+    if (i >= p.ntiles) return p.ntiles;
+    const int tiles_x = p.tiles_x, tiles_y = p.ntiles / tiles_x;
+    const int iw = p.txr - p.txl, ih = p.tyb - p.tyt;
+    const int nedge = p.ntiles - iw * ih;
+    int tx, ty;
+    if (i >= nedge) {  // interior, row-major
+        const int j = i - nedge;
+        ty = p.tyt + j / iw;
+        tx = p.txl + j % iw;
+    } else {
+        const int ntop = p.tyt * tiles_x, nbot = (tiles_y - p.tyb) * tiles_x;
+        if (i < ntop) {  // bands above the interior
+            ty = i / tiles_x;
+            tx = i % tiles_x;
+        } else if (i < ntop + nbot) {  // bands below it
+            const int j = i - ntop;
+            ty = p.tyb + j / tiles_x;
+            tx = j % tiles_x;
+        } else {  // left and right strips of the interior bands
+            const int j = i - ntop - nbot, per = p.txl + (tiles_x - p.txr);
+            ty = p.tyt + j / per;
+            const int m = j % per;
+            tx = m < p.txl ? m : p.txr + (m - p.txl);
+        }
+    }
+    return ty * tiles_x + tx;
+}
+
 template <typename T, int V, int K, int RM, int PF, bool VEC>
 __global__ __launch_bounds__(WAVE *WAVES_PER_BLOCK) void relax_tb_kernel(const KArgs p)
 {
     // the wave index is uniform across the wave; say so, so every tile quantity and
     // every row descriptor lives in scalar registers
     const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    const int tile = xcd_block() * WAVES_PER_BLOCK + wave;
+    const int tile = launch_tile(p, wave);
     if (tile >= p.ntiles) return;  // wave-uniform; waves never synchronise
     const int lane = threadIdx.x & (WAVE - 1);
     unsigned long long rmax = 0;
