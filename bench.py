@@ -46,12 +46,14 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
-TRAFFIC_SHA256 = "5fc53733956c7a11bcfb9b363e1eeb4897973f92042ba53011ee79de35a13af3"
+TRAFFIC_SHA256 = "a7eb3b0db2c737984662c4e16870326e715d134e14f2025902665c0283fea7d2"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 20): (226298.79, 131365.52), (8, 29): (211256.00, 131357.36), (8, 38): (192598.50, 131352.13),
-    (1, 12): (176105.12, 131275.71), (1, 16): (165582.29, 131276.66), (1, 20): (159090.86, 131277.77),
+    (8, 20): (195491.06, 131381.02), (8, 29): (180259.86, 131372.25), (8, 38): (170915.99, 131369.27),
+    (8, 47): (164044.46, 131367.90), (8, 56): (158679.01, 131365.44),
+    (1, 16): (167053.03, 131272.19), (1, 20): (160261.88, 131271.65), (1, 28): (152893.58, 131271.38),
 }
+VARIANT_ROWS = (12, 16, 20, 29, 38, 47)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
 
@@ -134,13 +136,22 @@ def variants(px, ctx, norms):
         d = setup(N, dt)
         ctx.reserve(N, d["phi0"].stride(0), px.dtype_code(d["phi0"]))
         for tb in range(1, 9):
+            # tile height for this k: the fastest of a few (one timed step each)
+            best_rows, best_t = 0, float("inf")
+            for rows in VARIANT_ROWS:
+                ctx.set_tile_rows(rows)
+                tr = time_region(relax_fn(px, d, ctx, norms, tb), reps=1, warmup=1)
+                if tr < best_t:
+                    best_rows, best_t = rows, tr
+            ctx.set_tile_rows(best_rows)
             reps = 3
-            t = time_region(relax_fn(px, d, ctx, norms, tb), reps=reps, warmup=2)
+            t = time_region(relax_fn(px, d, ctx, norms, tb), reps=reps, warmup=1)
+            ctx.set_tile_rows(0)
             launches = -(-SWEEPS // tb)
             gcell = N * N * SWEEPS * reps / t / 1e9
             gbs = BYTES_PER_CELL[dt] * N * N * launches * reps / t / 1e9
             out[f"fused_{dt}_k{tb}"] = {"gcell_s": round(gcell, 2), "alg_GBs": round(gbs, 1),
-                                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+                                        "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "tile_rows": best_rows}
             if dt == "f64" and tb == 1:
                 out["fused_f64_k1"]["frac_of_elementwise_ceiling"] = round(gbs / ceil, 4)
             log(f"  fused {dt} k={tb}: {gcell:8.1f} Gcell/s  {gbs:7.1f} GB/s algorithmic")
