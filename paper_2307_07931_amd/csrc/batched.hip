@@ -199,6 +199,35 @@ __global__ __launch_bounds__(BX) void copyback_rows_kernel(const RowArgs a)
     }
 }
 
+// Result of an odd number of relaxation launches back into the callers' grids, all
+// problems in one launch: block (x, p) copies rows x, x + gridDim.x, ... of problem p
+// from args[p].out to args[p].in (corners untouched, as by every relaxation).
+template <typename T>
+__global__ __launch_bounds__(BX) void copy_back_kernel(const KArgs *args)
+{
+    const KArgs q = args[blockIdx.y];
+    const int n = q.n;
+    const T *src = static_cast<const T *>(q.out);
+    T *dst = static_cast<T *>(const_cast<void *>(q.in));
+    for (int i = blockIdx.x; i <= n + 1; i += gridDim.x)
+        for (int j = threadIdx.x; j <= n + 1; j += BX) {
+            if ((i == 0 || i == n + 1) && (j == 0 || j == n + 1)) continue;
+            dst[(size_t)i * q.ld + j] = src[(size_t)i * q.ld + j];
+        }
+}
+
+hipError_t copy_back_launch(int dtype, const KArgs *args, int nprob, hipStream_t s)
+{
+    const dim3 g(64, nprob);
+    switch (dtype) {
+    case F64: hipLaunchKernelGGL((copy_back_kernel<double>), g, dim3(BX), 0, s, args); break;
+    case F32: hipLaunchKernelGGL((copy_back_kernel<float>), g, dim3(BX), 0, s, args); break;
+    case BF16: hipLaunchKernelGGL((copy_back_kernel<bf16>), g, dim3(BX), 0, s, args); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // Per-problem fixed-order reduction of contiguous partial slots [off[p], off[p+1]).
 __global__ __launch_bounds__(BX) void reduce_per_problem_kernel(const unsigned long long *pmax,
                                                                 const double *psum, const int *off,
@@ -430,10 +459,10 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
             e = hipGetLastError();
         }
     }
-    // an odd number of launches leaves the result in the scratch grids
+    // an odd number of launches leaves the result in the scratch grids: copy it back
+    // (the phi -> scratch arguments of any shape name both grids of every problem)
     if (e == hipSuccess && L % 2 == 1)
-        for (int p = 0; p < nprob && e == hipSuccess; ++p)
-            e = copy_grid_launch(dtype, base + tmp_off[p], probs[p].phi, probs[p].n, probs[p].ld, s);
+        e = copy_back_launch(dtype, dev_ptr<const KArgs>(base, shapes[seq[0]].args_off[0]), nprob, s);
     if (e != hipSuccess) {
         snprintf(err, errlen, "batched relaxation: %s", hipGetErrorString(e));
         return PX_EHIP;
@@ -445,7 +474,9 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
 
 // Tile rows per problem size: each size class relaxed alone (8 sweeps, one persistent
 // launch) for every candidate height, fastest of three timed runs after a warm-up.  Then
-// sweeps per launch for the whole batch: 24 sweeps at k = 1..8 with the tuned rows.
+// sweeps per launch for the whole batch, by time per sweep: at least 24 sweeps at k =
+// 1..8 with the tuned rows, an even number of launches each (so that no candidate pays
+// for copying the result back).
 int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int bc, hipStream_t s,
                    int *best_k, char *err, size_t errlen)
 {
@@ -503,12 +534,14 @@ int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob
     if (!st) {
         float bt = -1.f;
         for (int k = 1; k <= 8 && !st; ++k) {
+            const int sweeps = 2 * k * ((24 + 2 * k - 1) / (2 * k));
             const float ms = fastest([&] {
-                return batch_relax(w, dtype, probs, nprob, 24, k, bc, RES_NONE, nullptr, 0, s, err, errlen);
+                return batch_relax(w, dtype, probs, nprob, sweeps, k, bc, RES_NONE, nullptr, 0, s, err, errlen);
             }, 2);
             if (st) break;
-            if (bt < 0.f || ms < bt) {
-                bt = ms;
+            const float per = ms / sweeps;
+            if (bt < 0.f || per < bt) {
+                bt = per;
                 bk = k;
             }
         }

@@ -25,7 +25,8 @@ def ctx():
 SIZES = [1, 2, 7, 33, 64, 127, 130, 257, 64, 5, 300, 96]
 
 
-@pytest.mark.parametrize("dt,tblock,nsweeps", [("f64", 4, 13), ("f32", 8, 21), ("bf16", 3, 10), ("f64", 1, 3)])
+@pytest.mark.parametrize("dt,tblock,nsweeps", [("f64", 4, 13), ("f32", 8, 21), ("bf16", 3, 10), ("f64", 1, 3),
+                                               ("f64", 8, 24)])
 def test_relax_batched_equals_single_and_oracle(ctx, dt, tblock, nsweeps):
     items, refs = [], []
     for k, n in enumerate(SIZES):
