@@ -242,6 +242,7 @@ def mixed_workload(px, ctx):
     import numpy as np
     import torch
     import workloads as W
+    DEFAULT_INNER = {px.SOLVE_MIXED_F32: 1024, px.SOLVE_MIXED_BF16: 256}  # the library's defaults
     out = {"solves": [], "per_sweep_8192": {}}
     for n in (256, 512):
         f_host = W.grf_rhs(n, W.SEED_GRF_8192)
@@ -249,8 +250,8 @@ def mixed_workload(px, ctx):
         h = 1.0 / n
         lam = OMEGA * h * h / 4.0
         tune_sizes(px, ctx, n, f_host)
-        for mode, name, inner in ((px.SOLVE_PLAIN, "plain_f64", 0), (px.SOLVE_MIXED_F32, "mixed_f32", 64),
-                                  (px.SOLVE_MIXED_BF16, "mixed_bf16", 32)):
+        for mode, name, inner in ((px.SOLVE_PLAIN, "plain_f64", 0), (px.SOLVE_MIXED_F32, "mixed_f32", 0),
+                                  (px.SOLVE_MIXED_BF16, "mixed_bf16", 0)):
             phi = px.alloc_grid(n, torch.float64)
             f = px.alloc_rhs(n, torch.float64)
             f[:, :n] = torch.from_numpy(f_host).cuda()
@@ -258,7 +259,8 @@ def mixed_workload(px, ctx):
                           inner_sweeps=inner, raise_on_error=False)
             err = float(np.abs(phi[1:n + 1, 1:n + 1].cpu().numpy() - ex).max() / np.abs(ex).max())
             rec = {"n": n, "mode": name, "status": st.status, "sweeps": st.sweeps, "seconds": round(st.seconds, 3),
-                   "rel_res_max": st.rel_res_max, "rel_err_vs_exact": err}
+                   "rel_res_max": st.rel_res_max, "rel_err_vs_exact": err,
+                   "inner_sweeps": DEFAULT_INNER.get(mode, 0)}
             out["solves"].append(rec)
             log(f"  mixed/{n}: {rec}")
     # (b) 8192^2: time per sweep of each form
@@ -280,27 +282,41 @@ def mixed_workload(px, ctx):
                    "gcell_s": round(n * n * 64 * 5 / t / 1e9, 1)}
         del a, b, f, src
         torch.cuda.empty_cache()
-    # mixed solves at 8192^2 with budgets of 4 and 12 outer steps: the difference gives the
-    # time per inner sweep including the FP64 refinement step, without set-up costs
+    # mixed solves at 8192^2 (default inner sweeps) with budgets of 2 and 6 outer steps: the
+    # difference gives the time per inner sweep including the FP64 refinement step, without
+    # set-up costs
     phi = px.alloc_grid(n, torch.float64)
     f = px.alloc_rhs(n, torch.float64)
     f[:, :n] = torch.from_numpy(f_host).cuda()
-    for inner, mode in ((64, px.SOLVE_MIXED_F32), (32, px.SOLVE_MIXED_BF16)):
+    for mode in (px.SOLVE_MIXED_F32, px.SOLVE_MIXED_BF16):
+        inner = DEFAULT_INNER[mode]
         secs = []
-        for steps in (4, 12):
+        for steps in (2, 6):
             phi.zero_()
             st = px.solve(phi, n, f, h, lam, ctx, mode=mode, rtol=0.0, max_sweeps=inner * steps,
-                          inner_sweeps=inner, check_every=inner * steps, raise_on_error=False)
+                          check_every=inner * steps, raise_on_error=False)
             secs.append((st.seconds, st.sweeps))
         per["mixed_" + ("f32" if mode == px.SOLVE_MIXED_F32 else "bf16")] = {
             "s_per_sweep_incl_refine": (secs[1][0] - secs[0][0]) / (secs[1][1] - secs[0][1]), "inner": inner}
+    # the same number of sweeps from phi = 0 in each form: the residuals must track
+    track = 32768
+    for mode, key in ((px.SOLVE_PLAIN, "plain_f64"), (px.SOLVE_MIXED_F32, "mixed_f32"),
+                      (px.SOLVE_MIXED_BF16, "mixed_bf16")):
+        phi.zero_()
+        st = px.solve(phi, n, f, h, lam, ctx, mode=mode, rtol=0.0, max_sweeps=track, check_every=track,
+                      raise_on_error=False)
+        per.setdefault("residual_after_%d_sweeps" % track, {})[key] = st.rel_res_max
     g = slowest_mode_factor(n)
     floor = 5.6e-10  # FP64 attainable relative residual for this field at 8192^2 (exact solution rounded)
     tau = max(1e-10, 4 * floor)
     sweeps = math.log(tau) / math.log(g)
     t_plain = sweeps * per["f64"]["s_per_sweep"]
+    # sweeps to tolerance relative to plain FP64, as measured at 512^2
+    at512 = {r["mode"]: r["sweeps"] for r in out["solves"] if r["n"] == 512}
     for key in ("mixed_f32", "mixed_bf16"):
-        per[key]["extrapolated_seconds_to_tau"] = sweeps * per[key]["s_per_sweep_incl_refine"]
+        ratio = at512[key] / at512["plain_f64"]
+        per[key]["sweep_ratio_vs_plain_at_512"] = ratio
+        per[key]["extrapolated_seconds_to_tau"] = sweeps * ratio * per[key]["s_per_sweep_incl_refine"]
         per[key]["speedup_vs_plain_f64"] = t_plain / per[key]["extrapolated_seconds_to_tau"]
     per["plain_f64_extrapolated_seconds_to_tau"] = t_plain
     per["tau_eff"] = tau

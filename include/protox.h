@@ -181,7 +181,8 @@ typedef struct px_solve_opts {
     int check_every;       /* sweeps between residual checks (PLAIN); MIXED modes
                               read the norms back every check_every / inner_sweeps
                               outer steps (at least every step)                  */
-    int inner_sweeps;      /* sweeps per inner solve (MIXED)                     */
+    int inner_sweeps;      /* sweeps per inner solve (MIXED); 0 = default:
+                              1024 (FP32) or 256 (BF16)                          */
     int tblock;            /* sweeps per launch, 0 = default                     */
     int bc;                /* px_bc                                              */
 } px_solve_opts;

@@ -145,3 +145,31 @@ def test_mixed_failure_statuses(ctx):
         st = px.solve(phi, n, H.device_rhs(f, n, "f64"), h, 1.5 * h * h / 4, ctx, mode=px.SOLVE_MIXED_F32,
                       rtol=1e-14, inner_sweeps=32, raise_on_error=False)
         assert st.status in (px.EDIVERGED, px.ENONFINITE), (layout, st)
+
+
+@pytest.mark.parametrize("mode,inner,slack", [(px.SOLVE_MIXED_F32, 1024, 1.01), (px.SOLVE_MIXED_BF16, 256, 1.05)])
+def test_default_inner_converges_like_plain_fp64(ctx, mode, inner, slack):
+    """The default inner solves (1024 FP32 or 256 BF16 sweeps per FP64 step) reach
+    max|r| <= 1e-10 max|f| in about the sweeps plain FP64 relaxation needs -- the property
+    the time-to-tolerance comparison at large grids rests on -- with the error against the
+    exact discrete solution of the same size, and equal an explicit inner count of the same
+    size bit for bit."""
+    n = 128
+    f = W.grf_rhs(n, 109)
+    h = 1.0 / n
+    lam = OMEGA * h * h / 4.0
+    fd = H.device_rhs(f, n, "f64")
+    grids = [H.device_grid(np.zeros((n + 2, n + 2)), n, "f64") for _ in range(3)]
+    print(f"case: n={n} mode={mode} default inner vs plain FP64 and inner={inner}", flush=True)
+    plain = px.solve(grids[0], n, fd, h, lam, ctx, mode=px.SOLVE_PLAIN, rtol=1e-10)
+    mixed = px.solve(grids[1], n, fd, h, lam, ctx, mode=mode, rtol=1e-10)
+    explicit = px.solve(grids[2], n, fd, h, lam, ctx, mode=mode, rtol=1e-10, inner_sweeps=inner)
+    assert mixed.rel_res_max <= 1e-10
+    assert mixed.sweeps <= slack * plain.sweeps + inner, (mixed.sweeps, plain.sweeps)
+    assert mixed.sweeps % inner == 0
+    assert (mixed.sweeps, mixed.res_max) == (explicit.sweeps, explicit.res_max)
+    assert torch.equal(grids[1], grids[2])
+    ex = exact.dst_solve(f, h)
+    for g in grids[:2]:
+        err = np.abs(H.to_storage_np(g, "f64")[1:n + 1, 1:n + 1] - ex).max() / np.abs(ex).max()
+        assert err < 1e-8
