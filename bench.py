@@ -46,14 +46,13 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
-TRAFFIC_SHA256 = "a7eb3b0db2c737984662c4e16870326e715d134e14f2025902665c0283fea7d2"
+TRAFFIC_SHA256 = "3e9c4cf3ffcf8a84a87f40a86562b2324728fa52d8505d2ea1d3c2db68dfb358"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 20): (195491.06, 131381.02), (8, 29): (180259.86, 131372.25), (8, 38): (170915.99, 131369.27),
-    (8, 47): (164044.46, 131367.90), (8, 56): (158679.01, 131365.44),
-    (1, 16): (167053.03, 131272.19), (1, 20): (160261.88, 131271.65), (1, 28): (152893.58, 131271.38),
+    (8, 29): (180378.36, 131372.51), (8, 38): (171078.49, 131369.12), (8, 47): (164034.46, 131366.64),
+    (1, 20): (160270.27, 131271.69), (1, 47): (147379.19, 131271.51), (1, 64): (141636.57, 131268.72),
 }
-VARIANT_ROWS = (12, 16, 20, 29, 38, 47)  # tile heights tried for each fixed k in the variants
+VARIANT_ROWS = (12, 16, 20, 29, 38, 47, 64, 96)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
 
@@ -656,15 +655,21 @@ def main():
         hbm_view["traffic_write"] = round(tr["write"])
         hbm_view["traffic_over_algorithmic"] = round((tr["read"] + tr["write"]) / hbm_view["alg_bytes_per_launch"], 3)
         hbm_view["actual_GBs"] = round((tr["read"] + tr["write"]) / per_launch_s / 1e9, 1)
-    if tb == 1:
-        roofline = {"bound": "hbm", **hbm_view, "traffic": traffic}
+    # roofline: arithmetic intensity of a launch (k sweeps: 9k FLOP per 24 B of HBM traffic
+    # per cell) against the ridge point of the no-FMA FP64 peak over the HBM peak; below
+    # the ridge (every k <= 8: at most 3 FLOP/B against 4.9) the HBM roof binds
+    tflops = FLOPS_PER_CELL_SWEEP * N * N * tb / per_launch_s / 1e12
+    intensity = FLOPS_PER_CELL_SWEEP * tb / BYTES_PER_CELL["f64"]
+    ridge = FP64_NOFMA_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    alu_view = {"achieved": round(tflops, 3), "peak": round(FP64_NOFMA_PEAK_TFLOPS, 1), "unit": "TFLOP/s",
+                "frac": round(tflops / FP64_NOFMA_PEAK_TFLOPS, 4),
+                "alg_flops_per_launch": FLOPS_PER_CELL_SWEEP * N * N * tb}
+    if intensity < ridge:
+        roofline = {"bound": "hbm", **hbm_view, "traffic": traffic, "alu_view": alu_view}
     else:
-        # several sweeps per launch: HBM bytes per cell-update fall to 24/k and the
-        # kernel is bound by vector ALU issue
-        tflops = FLOPS_PER_CELL_SWEEP * N * N * tb / per_launch_s / 1e12
-        roofline = {"bound": "alu", "achieved": round(tflops, 3), "peak": round(FP64_NOFMA_PEAK_TFLOPS, 1),
-                    "unit": "TFLOP/s", "frac": round(tflops / FP64_NOFMA_PEAK_TFLOPS, 4), "traffic": traffic,
-                    "alg_flops_per_launch": FLOPS_PER_CELL_SWEEP * N * N * tb, "hbm_view": hbm_view}
+        roofline = {"bound": "alu", **{k: v for k, v in alu_view.items()}, "traffic": traffic, "hbm_view": hbm_view}
+    roofline["intensity_flop_per_byte"] = round(intensity, 3)
+    roofline["ridge_flop_per_byte"] = round(ridge, 3)
     roofline["kernel"] = f"relax_tb_kernel<double,2,{tb},*> ({rows or 'default'} rows per tile)"
 
     var = None if args.no_variants else variants(px, ctx, norms)

@@ -12,15 +12,18 @@ inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_
 
 int relax_default_rows(int dtype, int n, int sweeps)
 {
-    // Measured on MI355X at 4096^2: short bands win (more waves in flight); the
-    // recomputed halo rows (about 2*sweeps per band) favour about 32 rows at 5-8 sweeps.
-    // With sweeps + 1 a multiple of 3 the interior loop runs in blocks of sweeps + 1
-    // steps, so the band height is chosen with rows + 2*sweeps a multiple of sweeps + 1.
+    // Measured on MI355X at 4096^2 (edge tiles launched first): FP64 favours tall bands at
+    // 1-2 sweeps (fewer halo rows; waves stream long enough to hide latency), about 38 rows
+    // at 3-6 sweeps and about 30 at 7-8, where the recomputed halo rows (about 2*sweeps
+    // per band) weigh against the waves in flight; FP32 (256-column waves) about 20 rows
+    // up to 7 sweeps.  With sweeps + 1 a multiple of 3 the interior loop runs in blocks of
+    // sweeps + 1 steps, so the band height is chosen with rows + 2*sweeps a multiple of
+    // sweeps + 1.
     int rows;
     if (dtype == F64)
-        rows = sweeps <= 4 ? 16 : 32;
+        rows = sweeps <= 2 ? 48 : (sweeps <= 6 ? 38 : 32);
     else
-        rows = (sweeps == 3 || sweeps == 4) ? 16 : 32;
+        rows = sweeps <= 7 ? 20 : 32;
     // small grids are latency-bound: keep at least about 16 bands so more waves run at once
     rows = std::min(rows, std::max(8, (n + 2) / 16));
     if ((sweeps + 1) % 3 == 0) {
