@@ -241,7 +241,7 @@ def mixed_workload(px, ctx):
     import numpy as np
     import torch
     import workloads as W
-    DEFAULT_INNER = {px.SOLVE_MIXED_F32: 1024, px.SOLVE_MIXED_BF16: 256}  # the library's defaults
+    DEFAULT_INNER = {px.SOLVE_MIXED_F32: 1024, px.SOLVE_MIXED_BF16: 128}  # the library's defaults
     out = {"solves": [], "per_sweep_8192": {}}
     for n in (256, 512):
         f_host = W.grf_rhs(n, W.SEED_GRF_8192)

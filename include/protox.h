@@ -182,7 +182,7 @@ typedef struct px_solve_opts {
                               read the norms back every check_every / inner_sweeps
                               outer steps (at least every step)                  */
     int inner_sweeps;      /* sweeps per inner solve (MIXED); 0 = default:
-                              1024 (FP32) or 256 (BF16)                          */
+                              1024 (FP32) or 128 (BF16)                          */
     int tblock;            /* sweeps per launch, 0 = default                     */
     int bc;                /* px_bc                                              */
 } px_solve_opts;

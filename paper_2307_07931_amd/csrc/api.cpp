@@ -529,12 +529,16 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
 }
 
 // Default sweeps per inner solve of the mixed modes.  Long inner solves amortise the FP64
-// step (at 8192^2: 24 us per FP32 sweep with 1024 per step, 32 us with 64) and converged
-// in the same number of sweeps as plain FP64 relaxation on the grids measured; BF16 (an
-// 8-bit significand) is refined more often.  The same for every grid size, so a batch and
-// its members solved one by one take the same steps; a solve stops at the end of the
-// step that reaches the tolerance.
-static int default_inner(int mode) { return mode == PX_SOLVE_MIXED_F32 ? 1024 : 256; }
+// step (at 8192^2: 24 us per FP32 sweep with 1024 per step, 32 us with 64).  Each sweep
+// rounds the correction d to the storage type; after m sweeps d holds about m * lambda
+// times the residual, so the rounding leaves a high-frequency residual of about
+// eps * (8 / h^2) * m * lambda = 2 * omega * eps * m times |r| (eps = 2^-24 FP32, 2^-9
+// BF16).  Refinement converges while that stays below 1: FP32 with m = 1024 is at 1e-4
+// and takes exactly the sweeps of plain FP64; BF16 (an 8-bit significand) stalls near
+// m = 1024 and gets m = 128 (0.33).  The same for every grid size, so a batch and its
+// members solved one by one take the same steps; a solve stops at the end of the step
+// that reaches the tolerance.
+static int default_inner(int mode) { return mode == PX_SOLVE_MIXED_F32 ? 1024 : 128; }
 
 int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, double h, double lambda,
              const px_solve_opts *o, px_solve_stats *stats, px_ctx *ctx, void *stream)

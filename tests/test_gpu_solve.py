@@ -147,9 +147,9 @@ def test_mixed_failure_statuses(ctx):
         assert st.status in (px.EDIVERGED, px.ENONFINITE), (layout, st)
 
 
-@pytest.mark.parametrize("mode,inner,slack", [(px.SOLVE_MIXED_F32, 1024, 1.01), (px.SOLVE_MIXED_BF16, 256, 1.05)])
+@pytest.mark.parametrize("mode,inner,slack", [(px.SOLVE_MIXED_F32, 1024, 1.01), (px.SOLVE_MIXED_BF16, 128, 1.05)])
 def test_default_inner_converges_like_plain_fp64(ctx, mode, inner, slack):
-    """The default inner solves (1024 FP32 or 256 BF16 sweeps per FP64 step) reach
+    """The default inner solves (1024 FP32 or 128 BF16 sweeps per FP64 step) reach
     max|r| <= 1e-10 max|f| in about the sweeps plain FP64 relaxation needs -- the property
     the time-to-tolerance comparison at large grids rests on -- with the error against the
     exact discrete solution of the same size, and equal an explicit inner count of the same
