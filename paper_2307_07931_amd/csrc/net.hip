@@ -34,7 +34,11 @@ constexpr int NW2 = C * C * 9; // layer 2 / 3 weights
 constexpr int NW4 = C * 9;     // layer 4 weights
 constexpr int NPARAM = NW1 + 2 * NW2 + NW4;  // 19008
 constexpr int OFF2 = NW1, OFF3 = NW1 + NW2, OFF4 = NW1 + 2 * NW2;
-constexpr int WG_BLOCKS = 512; // split-K blocks of the weight gradients
+constexpr int WT_ROWS = 4;      // image rows per work unit of the thin layers' weight gradients
+constexpr int WT_WAVES = 8192;  // at most this many waves (and partial slots) for them
+constexpr int RS = 32;          // first-pass slices of the partial-sum reduction (32 -> 32 layers)
+constexpr int RS_THIN = 64;     // the same for the thin layers' 288 sums
+static_assert(RS_THIN * NW1 <= RS * NW2, "both slicings fit the middle buffer");
 constexpr int BX = 256;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -55,6 +59,8 @@ struct NetW {
     bf16 *w2b;  // [t][ci][co]  (input gradient: rows = input channel, k = output channel)
     bf16 *w3f, *w3b;
     bf16 *w4;   // [ci][t]
+    float *w1s, *w4s;  // the BF16 values of w1 and w4 as FP32, read by the thin layers with
+                       // wave-uniform addresses (scalar loads, so the weights sit in SGPRs)
 };
 
 __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restrict__ w, NetW nw)
@@ -64,6 +70,7 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
     const bf16 b = tobf(w[q]);
     if (q < OFF2) {
         nw.w1[q] = b;  // (co, 1, a, c) -> co*9 + t
+        nw.w1s[q] = bf16_to_f32(b.bits);
     } else if (q < OFF4) {
         const bool l3 = q >= OFF3;
         const int r = q - (l3 ? OFF3 : OFF2);
@@ -72,6 +79,7 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
         (l3 ? nw.w3b : nw.w2b)[(t * C + ci) * C + co] = b;
     } else {
         nw.w4[q - OFF4] = b;  // (1, ci, a, c) -> ci*9 + t
+        nw.w4s[q - OFF4] = bf16_to_f32(b.bits);
     }
 }
 
@@ -84,17 +92,15 @@ static_assert(LT_ROWS * LT_PX == BX, "one pixel per thread");
 // BF16, -> 32 channels, ReLU.  FP32 accumulation (fused multiply-add allowed).
 template <typename TX>
 __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, int ldx, double scale,
-                                                    const bf16 *__restrict__ w1, bf16 *__restrict__ a1, int B,
+                                                    const float *__restrict__ sw, bf16 *__restrict__ a1, int B,
                                                     int H, int W)
 {
 #pragma clang fp contract(fast)
-    __shared__ float sw[NW1];
     __shared__ float sx[(LT_ROWS + 2) * (LT_PX + 2)];
     const int tiles_w = (W + LT_PX - 1) / LT_PX, tiles_h = (H + LT_ROWS - 1) / LT_ROWS;
     const int tw = (int)(blockIdx.x % tiles_w), th = (int)((blockIdx.x / tiles_w) % tiles_h);
     const int b = (int)(blockIdx.x / ((unsigned)tiles_w * tiles_h));
     const int i0 = th * LT_ROWS, j0 = tw * LT_PX;
-    for (int q = threadIdx.x; q < NW1; q += BX) sw[q] = bfv(w1[q]);
     for (int q = threadIdx.x; q < (LT_ROWS + 2) * (LT_PX + 2); q += BX) {
         const int pr = q / (LT_PX + 2), pc = q % (LT_PX + 2);
         const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
@@ -246,17 +252,19 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
 // Layer 4: 32 channels -> 1, output FP32 into rows of ldy.  The a3 patch (6 x 66 pixels,
 // rows padded to PSTR elements) and the weights are staged in LDS; each thread reads its
 // 9 neighbours' 32 channels as 16-byte LDS loads.
-__global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const bf16 *__restrict__ w4,
+__global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const float *__restrict__ w4s,
                                                     float *__restrict__ y, int ldy, int B, int H, int W)
 {
 #pragma clang fp contract(fast)
-    __shared__ float sw[NW4];
+    // weights tap-major in LDS: the 8 channels of one 16-byte activation read take their
+    // 8 weights with two 16-byte reads (the same address in every lane)
+    __shared__ __align__(16) float sw[9 * C];
     __shared__ __align__(16) bf16 sp[(LT_ROWS + 2) * (LT_PX + 2) * PSTR];
     const int tiles_w = (W + LT_PX - 1) / LT_PX, tiles_h = (H + LT_ROWS - 1) / LT_ROWS;
     const int tw = (int)(blockIdx.x % tiles_w), th = (int)((blockIdx.x / tiles_w) % tiles_h);
     const int b = (int)(blockIdx.x / ((unsigned)tiles_w * tiles_h));
     const int i0 = th * LT_ROWS, j0 = tw * LT_PX;
-    for (int q = threadIdx.x; q < NW4; q += BX) sw[q] = bfv(w4[q]);
+    for (int q = threadIdx.x; q < NW4; q += BX) sw[(q % 9) * C + q / 9] = w4s[q];
     for (int q = threadIdx.x; q < (LT_ROWS + 2) * (LT_PX + 2) * 4; q += BX) {
         const int ch = q & 3, pc = (q >> 2) % (LT_PX + 2), pr = (q >> 2) / (LT_PX + 2);
         const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
@@ -276,11 +284,14 @@ __global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3,
 #pragma unroll
         for (int c8 = 0; c8 < 4; ++c8) {
             const uint4 u = *reinterpret_cast<const uint4 *>(px + c8 * 8);
+            const float4 wa = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8);
+            const float4 wb = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8 + 4);
+            const float wv[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
             const unsigned wd[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                acc += sw[(c8 * 8 + 2 * e) * 9 + t] * __uint_as_float(wd[e] << 16);
-                acc += sw[(c8 * 8 + 2 * e + 1) * 9 + t] * __uint_as_float(wd[e] & 0xffff0000u);
+                acc += wv[2 * e] * __uint_as_float(wd[e] << 16);
+                acc += wv[2 * e + 1] * __uint_as_float(wd[e] & 0xffff0000u);
             }
         }
     }
@@ -502,66 +513,116 @@ __global__ __launch_bounds__(64) void wgrad32_mfma_kernel(const bf16 *__restrict
         for (int r = 0; r < 16; ++r) dst[((8 * (r / 4) + 4 * kg + r % 4) * C + n) * 9 + t] = acc[t][r];
 }
 
-// Weight gradients of the thin layers, split over WG_BLOCKS pixel ranges; thread (channel,
-// tap) sums over its block's range row by row (no division per pixel), four interleaved
-// partial sums for instruction-level parallelism, combined in a fixed order.
-//   layer 1: part[blk][co*9 + t] = sum dz1[p][co] * a0[p + off_t]  (a0 = BF16 of x, as the
+// Weight gradients of the thin layers.  Work units of WT_ROWS image rows x 64 columns of
+// one image; one wave per unit (waves beyond WT_WAVES take further units in a fixed
+// stride, adding into the same slot).  Lane (c = lane mod 32, half = lane / 32) owns
+// channel c and 32 of the unit's columns: along each row it slides a 3 x 3 window of the
+// shifted operand (three new loads per pixel, coalesced over the 32 channel lanes or the
+// same address for all), multiplies by the pixel's own operand and keeps the 9 tap sums
+// in registers.  The two halves are added (lower half first) and the 288 sums of the wave
+// written to its slot.
+//   layer 1: part[slot][co*9 + t] = sum dz1[p][co] * a0[p + off_t]  (a0 = BF16 of x, as the
 //            forward pass used)
-//   layer 4: part[blk][ci*9 + t] = sum dy[p] * a3[p + off_t][ci]
+//   layer 4: part[slot][ci*9 + t] = sum dy[p] * a3[p + off_t][ci]
 template <bool L4>
-__global__ __launch_bounds__(NW1) void wgrad_thin_kernel(const float *__restrict__ x, int ldx,
-                                                         const bf16 *__restrict__ a3, const float *__restrict__ dy,
-                                                         const bf16 *__restrict__ dz1, float *__restrict__ part,
-                                                         int B, int H, int W)
+__global__ __launch_bounds__(64) void wgrad_thin_kernel(const float *__restrict__ x, int ldx,
+                                                        const bf16 *__restrict__ a3, const float *__restrict__ dy,
+                                                        const bf16 *__restrict__ dz1, float *__restrict__ part,
+                                                        int B, int H, int W)
 {
-    static_assert(NW1 == NW4, "one block shape for both thin layers");
-    const long long N = (long long)B * H * W;
-    const long long p0 = N * blockIdx.x / gridDim.x, p1 = N * (blockIdx.x + 1) / gridDim.x;
-    const int ch = threadIdx.x / 9, t = threadIdx.x % 9;
-    const int dyo = tap_dy(t, false), dxo = tap_dx(t, false);
-    float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-    long long p = p0;
-    long long row = p0 / W;  // b * H + i
-    int j = (int)(p0 - row * W);
-    while (p < p1) {
-        const int i = (int)(row % H);
-        const long long b = row / H;
-        const int jend = (int)min((long long)W, (long long)j + (p1 - p));
-        const int ii = i + dyo;
-        const bool rowok = ii >= 0 && ii < H;
-        const long long srow = (b * H + (rowok ? ii : 0));  // source row (used only if rowok)
-        auto term = [&](int jj) -> float {
-            const int c = jj + dxo;
-            const bool ok = rowok && c >= 0 && c < W;
-            if (L4) {
-                const float s = ok ? bfv(a3[(srow * W + c) * C + ch]) : 0.0f;
-                return dy[row * W + jj] * s;
-            } else {
-                const float a0 = ok ? bf16_to_f32(f32_to_bf16_rne(x[srow * ldx + c])) : 0.0f;
-                return bfv(dz1[(row * W + jj) * C + ch]) * a0;
-            }
-        };
-        int jj = j;
-        for (; jj + 4 <= jend; jj += 4) {
+    static_assert(NW1 == NW4, "one partial layout for both thin layers");
+    const int strips = (W + 63) / 64, groups = (H + WT_ROWS - 1) / WT_ROWS;
+    const long long units = (long long)B * groups * strips;
+    const int lane = threadIdx.x, ch = lane & 31, half = lane >> 5;
+    float acc[9];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc[u] += term(jj + u);
+    for (int t = 0; t < 9; ++t) acc[t] = 0.0f;
+    for (long long u = blockIdx.x; u < units; u += gridDim.x) {
+        const int b = (int)(u / ((long long)groups * strips));
+        const int rem = (int)(u % ((long long)groups * strips));
+        const int i0 = (rem / strips) * WT_ROWS, i1 = min(i0 + WT_ROWS, H);
+        const int j0 = (rem % strips) * 64 + half * 32, j1 = min(j0 + 32, W);
+        const long long img = (long long)b * H;
+        for (int i = i0; i < i1; ++i) {
+            if (j0 >= j1) break;
+            // the three source rows of this output row (null outside the image), so the
+            // loads below index with 32-bit column offsets
+            const bf16 *ra[3];
+            const float *rx[3];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                const int ii = i + r - 1;
+                const bool in = ii >= 0 && ii < H;
+                ra[r] = (L4 && in) ? a3 + ((img + ii) * W) * C + ch : nullptr;
+                rx[r] = (!L4 && in) ? x + (img + ii) * ldx : nullptr;
+            }
+            // shifted operand of source row r at column jj, zero outside the image
+            auto sh = [&](int r, int jj) -> float {
+                const bool ok = jj >= 0 && jj < W;
+                if (L4) return (ra[r] && ok) ? bfv(ra[r][jj * C]) : 0.0f;
+                return (rx[r] && ok) ? bf16_to_f32(f32_to_bf16_rne(rx[r][jj])) : 0.0f;
+            };
+            float w0[3], w1[3], w2[3];  // columns j - 1, j, j + 1 of rows i - 1, i, i + 1
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                w0[r] = sh(r, j0 - 1);
+                w1[r] = sh(r, j0);
+            }
+            // four pixels per step: all their loads are issued before the products, so
+            // a wave keeps 16 loads in flight instead of waiting on each pixel's
+            for (int j = j0; j < j1; j += 4) {
+                float nw[4][3], pv[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) nw[e][r] = sh(r, j + e + 1);
+                    const long long q = (img + i) * W + j + e;
+                    pv[e] = (j + e < j1) ? (L4 ? dy[q] : bfv(dz1[q * C + ch])) : 0.0f;
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        w2[r] = nw[e][r];
+                        acc[3 * r] = fmaf(pv[e], w0[r], acc[3 * r]);
+                        acc[3 * r + 1] = fmaf(pv[e], w1[r], acc[3 * r + 1]);
+                        acc[3 * r + 2] = fmaf(pv[e], w2[r], acc[3 * r + 2]);
+                        w0[r] = w1[r];
+                        w1[r] = w2[r];
+                    }
+                }
+            }
         }
-        for (; jj < jend; ++jj) acc[0] += term(jj);
-        p += jend - j;
-        j = 0;
-        row += 1;
     }
-    part[(size_t)blockIdx.x * NW1 + threadIdx.x] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const float other = __shfl_down(acc[t], 32, 64);
+        if (half == 0) part[(size_t)blockIdx.x * NW1 + ch * 9 + t] = acc[t] + other;
+    }
 }
 
-// g[off + q] = sum over blocks (in block order) of part[blk][q].
-__global__ __launch_bounds__(BX) void reduce_wgrad_kernel(const float *__restrict__ part, int nblk, int count,
+// g[q] = sum over slots of part[slot][q], in two passes with a fixed split: slice s of
+// gridDim.y adds its contiguous run of slots in order into mid[s][q]; then the slices are
+// added in order.  Deterministic, and wide enough to keep the whole chip busy.
+__global__ __launch_bounds__(BX) void reduce_wgrad_slices_kernel(const float *__restrict__ part, int nblk, int count,
+                                                                 float *__restrict__ mid)
+{
+    const int q = blockIdx.x * BX + threadIdx.x;
+    if (q >= count) return;
+    const int ns = gridDim.y;
+    const int k0 = (int)((long long)nblk * blockIdx.y / ns), k1 = (int)((long long)nblk * (blockIdx.y + 1) / ns);
+    float s = 0.0f;
+    for (int k = k0; k < k1; ++k) s += part[(size_t)k * count + q];
+    mid[(size_t)blockIdx.y * count + q] = s;
+}
+
+__global__ __launch_bounds__(BX) void reduce_wgrad_kernel(const float *__restrict__ mid, int ns, int count,
                                                           float *__restrict__ g)
 {
     const int q = blockIdx.x * BX + threadIdx.x;
     if (q >= count) return;
     float s = 0.0f;
-    for (int k = 0; k < nblk; ++k) s += part[(size_t)k * count + q];
+    for (int k = 0; k < ns; ++k) s += mid[(size_t)k * count + q];
     g[q] = s;
 }
 
@@ -724,7 +785,7 @@ struct NetState {
     NetW nw{};
     long long pixels = 0;  // workspace capacity
     bf16 *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *dz1 = nullptr, *dz2 = nullptr, *dz3 = nullptr;
-    float *y = nullptr, *dy = nullptr, *part = nullptr;
+    float *y = nullptr, *dy = nullptr, *part = nullptr, *mid = nullptr, *ws = nullptr;
     double *dpart = nullptr;
     long long step = 0;
     long long last_pixels = 0;  // pixels of the last forward pass (0: none yet)
@@ -746,7 +807,7 @@ struct NetState {
     ~NetState()
     {
         free_workspace();
-        for (float **p : {&w, &m, &v, &g, &part}) {
+        for (float **p : {&w, &m, &v, &g, &part, &mid, &ws}) {
             if (*p) (void)hipFree(*p);
             *p = nullptr;
         }
@@ -766,7 +827,12 @@ hipError_t net_alloc(NetState &s)
     s.nw.w3f = s.nw.w2b + NW2;
     s.nw.w3b = s.nw.w3f + NW2;
     s.nw.w4 = s.nw.w3b + NW2;
-    return hipMalloc(&s.part, sizeof(float) * (size_t)std::max(WG_BLOCKS, WGM_BLOCKS) * NW2);
+    if ((e = hipMalloc(&s.ws, sizeof(float) * (NW1 + NW4))) != hipSuccess) return e;
+    s.nw.w1s = s.ws;
+    s.nw.w4s = s.ws + NW1;
+    static_assert((size_t)WT_WAVES * NW1 <= (size_t)WGM_BLOCKS * NW2, "thin partials fit the partial buffer");
+    if ((e = hipMalloc(&s.mid, sizeof(float) * (size_t)RS * NW2)) != hipSuccess) return e;
+    return hipMalloc(&s.part, sizeof(float) * (size_t)WGM_BLOCKS * NW2);
 }
 
 hipError_t net_set(NetState &s, const float *host)
@@ -818,16 +884,16 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
     if (e != hipSuccess) return e;
     const unsigned lt = thin_blocks(B, H, W);
     if (xdt == F64)
-        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(lt), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1,
+        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(lt), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1s,
                            s.a1, B, H, W);
     else
-        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(lt), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1,
+        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(lt), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1s,
                            s.a1, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a1, s.nw.w2f, s.a2,
                        (const bf16 *)nullptr, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
                        (const bf16 *)nullptr, B, H, W);
-    hipLaunchKernelGGL(l4_fwd_kernel, dim3(lt), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(lt), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
     s.last_pixels = N;
     return hipGetLastError();
 }
@@ -852,26 +918,31 @@ hipError_t net_gradient(NetState &s, const float *x, const float *t, int B, int 
     const unsigned cb = conv_blocks(B, H, W);
     const unsigned wgm = (unsigned)std::min<long long>(
         (long long)B * ((W + 63) / 64) * ((H + WG_ROWS - 1) / WG_ROWS), WGM_BLOCKS);
+    const unsigned wtn = (unsigned)std::min<long long>(
+        (long long)B * ((W + 63) / 64) * ((H + WT_ROWS - 1) / WT_ROWS), WT_WAVES);
+    auto reduce = [&](unsigned nblk, int count, float *g) {
+        const int ns = count == NW2 ? RS : RS_THIN;
+        hipLaunchKernelGGL(reduce_wgrad_slices_kernel, dim3(blocks_for(count), ns), dim3(BX), 0, st, s.part,
+                           (int)nblk, count, s.mid);
+        hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(count)), dim3(BX), 0, st, s.mid, ns, count, g);
+    };
     // layer 4
-    hipLaunchKernelGGL(wgrad_thin_kernel<true>, dim3(WG_BLOCKS), dim3(NW4), 0, st, (const float *)nullptr, 0, s.a3,
-                       s.dy, (const bf16 *)nullptr, s.part, B, H, W);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW4)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW4,
-                       s.g + OFF4);
+    hipLaunchKernelGGL(wgrad_thin_kernel<true>, dim3(wtn), dim3(64), 0, st, (const float *)nullptr, 0, s.a3, s.dy,
+                       (const bf16 *)nullptr, s.part, B, H, W);
+    reduce(wtn, NW4, s.g + OFF4);
     hipLaunchKernelGGL(l4_bwd_kernel, dim3(blocks_for(N)), dim3(BX), 0, st, s.dy, s.nw.w4, s.a3, s.dz3, B, H, W);
     // layer 3
     hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3(wgm), dim3(64), 0, st, s.a2, s.dz3, s.part, B, H, W);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, (int)wgm, NW2,
-                       s.g + OFF3);
+    reduce(wgm, NW2, s.g + OFF3);
     hipLaunchKernelGGL(conv32_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz3, s.nw.w3b, s.dz2, s.a2, B, H, W);
     // layer 2
     hipLaunchKernelGGL(wgrad32_mfma_kernel, dim3(wgm), dim3(64), 0, st, s.a1, s.dz2, s.part, B, H, W);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW2)), dim3(BX), 0, st, s.part, (int)wgm, NW2,
-                       s.g + OFF2);
+    reduce(wgm, NW2, s.g + OFF2);
     hipLaunchKernelGGL(conv32_kernel<true>, dim3(cb), dim3(BX), 0, st, s.dz2, s.nw.w2b, s.dz1, s.a1, B, H, W);
     // layer 1
-    hipLaunchKernelGGL(wgrad_thin_kernel<false>, dim3(WG_BLOCKS), dim3(NW1), 0, st, x, W, (const bf16 *)nullptr,
+    hipLaunchKernelGGL(wgrad_thin_kernel<false>, dim3(wtn), dim3(64), 0, st, x, W, (const bf16 *)nullptr,
                        (const float *)nullptr, s.dz1, s.part, B, H, W);
-    hipLaunchKernelGGL(reduce_wgrad_kernel, dim3(blocks_for(NW1)), dim3(BX), 0, st, s.part, WG_BLOCKS, NW1, s.g);
+    reduce(wtn, NW1, s.g);
     return hipGetLastError();
 }
 
