@@ -438,7 +438,7 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
     // recomputation; the best also depends on how the wave count divides the
     // resident wave slots, so the list is dense.
     // (29, 38 and 47 make rows + 2k a multiple of k + 1 at k = 8, whole unrolled step blocks)
-    static const int ROWS[] = {8, 12, 16, 20, 24, 28, 29, 32, 36, 38, 40, 44, 47, 48, 56, 64, 80, 96, 128};
+    static const int ROWS[] = {4, 6, 8, 12, 16, 20, 24, 28, 29, 32, 36, 38, 40, 44, 47, 48, 56, 64, 80, 96, 128};
     const double h = 1.0 / n, lambda = 0.25 * h * h * (2.0 / 3.0);
     hipEvent_t e0, e1;
     PX_HIP(hipEventCreate(&e0), "hipEventCreate");

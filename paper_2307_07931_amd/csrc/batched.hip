@@ -480,7 +480,7 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
 int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int bc, hipStream_t s,
                    int *best_k, char *err, size_t errlen)
 {
-    static const int ROWS[] = {8, 12, 16, 20, 24, 29, 32, 38, 40, 48, 64, 96, 128};
+    static const int ROWS[] = {4, 6, 8, 12, 16, 20, 24, 29, 32, 38, 40, 48, 64, 96, 128};
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
         snprintf(err, errlen, "hipEventCreate failed");
