@@ -15,7 +15,10 @@
 //     shift, so no LDS and no barriers are needed -- waves are independent;
 //   * the wave recomputes a halo of NL columns on each side and NL rows above
 //     and below its band (overlapped tiling), so a tile's output depends only
-//     on what the tile itself loaded.  Output columns per wave: `stride`.
+//     on what the tile itself loaded.  Output columns per wave: `stride`.  (One
+//     level: no column halo -- aligned strips, single-element neighbour loads.)
+//   * edge tiles are launched first, then the interior in XCD-contiguous runs;
+//     odd bands stream upwards, so neighbouring bands share halo rows via L2.
 // Boundary: DIRICHLET0 replaces the neighbour across the boundary face by
 // -(centre) at every level (odd reflection applied on the fly); GHOST_FIXED
 // keeps ghost cells as fixed points of every level.
@@ -576,9 +579,6 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 // delivers each row differs.  Bands alternate direction, so two neighbouring bands read the
 // 2K rows they share at the same end of their lives (both first or both last) while they
 // run side by side, and the second read of a shared row tends to hit the L2.
-#ifndef PX_ALT_DIR
-#define PX_ALT_DIR 1
-#endif
 template <typename T, int V, int K, bool VEC, bool FILLING, bool UP, bool EDGE>
 __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, int s0, int base,
                                               typename Elem<T>::A (&win)[K][3][V],
@@ -747,7 +747,7 @@ __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lan
     const bool interior = c0 >= 1 && c0 + WAVE * V - 1 <= n && y0 - NL >= 1 && y1 + NL - 1 <= n;
     const Tile tl{n, oc0, oc1, mc, y0, y1, whole};
     if constexpr (RM == RES_NONE && (K + 1) % 3 == 0) {
-        const bool up = PX_ALT_DIR && (ty & 1);
+        const bool up = (ty & 1) != 0;
         if (interior) {
             if (up)
                 run_tile_renamed<T, V, K, VEC, true, false>(p, tl);
@@ -792,10 +792,10 @@ __device__ __forceinline__ int xcd_block()
 }
 
 // Launch order.  Edge tiles (boundary substitution and ghost writes: longer-lived than
-// interior waves, by a factor up to 2.5 where they take run_tile) go first, spread over all XCDs,
-// so that no slow wave starts near the end of the launch and stretches its tail; the
-// interior tiles follow, each XCD taking a contiguous run.  Returns the tile index
-// (ty * tiles_x + tx), or ntiles for a wave without a tile.
+// interior waves, by a factor up to 2.5 where they take run_tile) go first, spread over
+// all XCDs, so that no slow wave starts near the end of the launch and stretches its
+// tail; the interior tiles follow, each XCD taking a contiguous run.  Returns the tile
+// index (ty * tiles_x + tx), or ntiles for a wave without a tile.
 __device__ __forceinline__ int launch_tile(const KArgs &p, int wave)
 {
     if (!p.edge_first) return xcd_block() * WAVES_PER_BLOCK + wave;
