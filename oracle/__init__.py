@@ -28,6 +28,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 
 BC_DIRICHLET0 = 0
 BC_GHOST_FIXED = 1
+BC_PERIODIC = 2
 RES_NONE, RES_LAGGED, RES_FINAL = 0, 1, 2
 
 LAPLACE_TAPS = (0.0, 1.0, 0.0, 1.0, -4.0, 1.0, 0.0, 1.0, 0.0)

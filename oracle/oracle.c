@@ -36,7 +36,10 @@
  *     interior) (reflection in both directions).  The alternative
  *     GHOST_FIXED mode reads the ghost ring as given and never changes it
  *     (the literal behaviour of the paper's generated code, which reads
- *     ghost cells and never writes them);
+ *     ghost cells and never writes them).  PERIODIC (Proto's own boundary,
+ *     Section II) wraps the grid into a torus: each ghost is a copy of the
+ *     interior cell n cells away (corners included), refreshed before every
+ *     sweep and written with the output;
  *   - residual vector:  r = rho - (1/h^2) s.  The paper's norm takes
  *     |(1/h^2) s - rho|, which is the same number bit for bit;
  *   - the max is NaN-propagating (a NaN residual makes the norm NaN);
@@ -59,7 +62,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OX_BC_DIRICHLET0 = 0, OX_BC_GHOST_FIXED = 1 };
+enum { OX_BC_DIRICHLET0 = 0, OX_BC_GHOST_FIXED = 1, OX_BC_PERIODIC = 2 };
 enum { OX_RES_NONE = 0, OX_RES_LAGGED = 1, OX_RES_FINAL = 2 };
 
 /* ------------------------------------------------------------------ */
@@ -125,6 +128,18 @@ static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, const int bcs[4])   
         if (bcs[2] == OX_BC_DIRICHLET0) w[(size_t)k * m + 0] = -w[(size_t)k * m + 1];\
         if (bcs[3] == OX_BC_DIRICHLET0)                                              \
             w[(size_t)k * m + (n + 1)] = -w[(size_t)k * m + n];                      \
+    }                                                                                \
+    for (int k = 1; k <= n; ++k) {                                                   \
+        if (bcs[0] == OX_BC_PERIODIC) w[(size_t)0 * m + k] = w[(size_t)n * m + k];   \
+        if (bcs[1] == OX_BC_PERIODIC) w[(size_t)(n + 1) * m + k] = w[(size_t)1 * m + k]; \
+        if (bcs[2] == OX_BC_PERIODIC) w[(size_t)k * m + 0] = w[(size_t)k * m + n];   \
+        if (bcs[3] == OX_BC_PERIODIC) w[(size_t)k * m + (n + 1)] = w[(size_t)k * m + 1]; \
+    }                                                                                \
+    if (bcs[0] == OX_BC_PERIODIC && bcs[2] == OX_BC_PERIODIC) {                      \
+        w[0] = w[(size_t)n * m + n];                                                 \
+        w[n + 1] = w[(size_t)n * m + 1];                                             \
+        w[(size_t)(n + 1) * m + 0] = w[(size_t)1 * m + n];                           \
+        w[(size_t)(n + 1) * m + n + 1] = w[(size_t)1 * m + 1];                       \
     }                                                                                \
     if (bcs[0] == OX_BC_DIRICHLET0 && bcs[2] == OX_BC_DIRICHLET0)                    \
         w[0] = w[(size_t)1 * m + 1];                                                 \
@@ -193,8 +208,9 @@ static void norm_pass_##SUF(const AT *temp, int n, const ST *f, int ld_f, AT c, 
 }                                                                                    \
                                                                                      \
 /* Output ghost ring of a freshly written phi_out, per side: odd reflection of the \
- * new interior (DIRICHLET0), or the input's ghosts unchanged (GHOST_FIXED).  The \
- * four corner cells are left untouched. */                                          \
+ * new interior (DIRICHLET0), the input's ghosts unchanged (GHOST_FIXED), or the   \
+ * new interior n cells away (PERIODIC).  The four corner cells are left untouched \
+ * except on a torus, where they are the opposite interior corners. */             \
 static void write_out_ghosts_##SUF(const ST *in, ST *out, int n, int ld, const int bcs[4]) \
 {                                                                                    \
     for (int k = 1; k <= n; ++k) {                                                   \
@@ -202,9 +218,18 @@ static void write_out_ghosts_##SUF(const ST *in, ST *out, int n, int ld, const i
                        (size_t)k * ld + 0, (size_t)k * ld + n + 1};                  \
         size_t a[4] = {(size_t)1 * ld + k, (size_t)n * ld + k,                       \
                        (size_t)k * ld + 1, (size_t)k * ld + n};                      \
+        size_t o[4] = {(size_t)n * ld + k, (size_t)1 * ld + k,                       \
+                       (size_t)k * ld + n, (size_t)k * ld + 1};                      \
         for (int side = 0; side < 4; ++side)                                         \
             out[g[side]] = (bcs[side] == OX_BC_DIRICHLET0) ? STORE(-LOAD(out[a[side]])) \
+                           : (bcs[side] == OX_BC_PERIODIC) ? out[o[side]]            \
                                                            : in[g[side]];            \
+    }                                                                                \
+    if (bcs[0] == OX_BC_PERIODIC && bcs[2] == OX_BC_PERIODIC) {                      \
+        out[0] = out[(size_t)n * ld + n];                                            \
+        out[n + 1] = out[(size_t)n * ld + 1];                                        \
+        out[(size_t)(n + 1) * ld] = out[(size_t)1 * ld + n];                         \
+        out[(size_t)(n + 1) * ld + n + 1] = out[(size_t)1 * ld + 1];                 \
     }                                                                                \
 }                                                                                    \
                                                                                      \
@@ -281,8 +306,9 @@ void ox_sweep_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, int ld_f,
                                                                                      \
 /* nsweeps sweeps in -> out (in is not modified; out gets the final iterate).       \
  * resmode LAGGED: norms of the last sweep's input; FINAL: norms of out.            \
- * nsweeps == 0 copies in to out.  The four corner cells of out are never         \
- * written (the 5-point stencil does not read them).  bcs: per-side modes      \
+ * nsweeps == 0 copies in to out.  The four corner cells of out are not written   \
+ * (the 5-point stencil does not read them), except on a torus (all sides          \
+ * PERIODIC), where they are the opposite interior corners.  bcs: per-side modes  \
  * (north, south, west, east); a GHOST_FIXED side models a box interface whose    \
  * ghost layer was filled from a neighbouring box before the sweeps. */           \
 void ox_relax_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,         \
@@ -300,10 +326,11 @@ void ox_relax_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,    
         ox_sweep_sides_##SUF(a, b, n, ld, f, ld_f, h, lambda, bcs, nrm);             \
         ST *t = a; a = b; b = t;                                                     \
     }                                                                                \
+    const int torus = bcs[0] == OX_BC_PERIODIC && bcs[2] == OX_BC_PERIODIC;         \
     for (int i = 0; i < m; ++i)                                                      \
         for (int j = 0; j < m; ++j) {                                                \
             int corner = (i == 0 || i == m - 1) && (j == 0 || j == m - 1);           \
-            if (!corner) out[(size_t)i * ld + j] = a[(size_t)i * ld + j];            \
+            if (!corner || (torus && nsweeps > 0)) out[(size_t)i * ld + j] = a[(size_t)i * ld + j]; \
         }                                                                            \
     if (resmode == OX_RES_FINAL)                                                     \
         ox_residual_sides_##SUF(a, n, ld, f, ld_f, h, bcs, NULL, 0, norms);          \

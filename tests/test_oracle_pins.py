@@ -334,3 +334,102 @@ def test_window_with_fixed_interface_ghosts_matches_full_grid():
     F = oracle.BC_GHOST_FIXED
     out, _, _ = oracle.relax_sides(pw, fw, B, h, lam, N, (F, F, F, F), resmode=oracle.RES_NONE)
     assert np.any(out[N - 1, N:B + 2 - N] != full[9 + N - 1, 11 + N:11 + B + 2 - N])
+
+
+# ------------------------------------------------------ periodic variant --
+# On a torus (Proto's own boundary) the discrete Fourier modes are the eigenvectors of
+# the 5-point stencil: S cos(2 pi (p i + q j) / n) = -4 (sin^2(pi p / n) + sin^2(pi q / n))
+# times the mode, so with f = 0 one sweep multiplies the mode by
+# g = 1 - omega (sin^2(pi p / n) + sin^2(pi q / n)).
+
+def periodic_mode(n, p, q):
+    i = np.arange(1, n + 1)[:, None]
+    j = np.arange(1, n + 1)[None, :]
+    return np.cos(2 * np.pi * (p * i + q * j) / n + 0.3)
+
+
+def torus_laplacian(n, h):
+    """Dense periodic 5-point Laplacian (circulant), written out cell by cell."""
+    A = np.zeros((n * n, n * n))
+    for i in range(n):
+        for j in range(n):
+            k = i * n + j
+            A[k, k] -= 4.0
+            for di, dj in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+                A[k, ((i + di) % n) * n + (j + dj) % n] += 1.0
+    return A / (h * h)
+
+
+@pytest.mark.parametrize("p,q", [(0, 1), (1, 1), (2, 5), (8, 0), (8, 8), (3, 13)])
+def test_periodic_mode_damping(p, q):
+    n, N = 16, 30
+    h, lam = lam_of(n)
+    mode = periodic_mode(n, p, q)
+    out, _, _ = oracle.relax(W.embed(mode, n, n + 2), np.zeros((n, n)), n, h, lam, N,
+                             bc=oracle.BC_PERIODIC, resmode=oracle.RES_NONE)
+    g = 1.0 - OMEGA * (np.sin(np.pi * p / n) ** 2 + np.sin(np.pi * q / n) ** 2)
+    np.testing.assert_allclose(out[1:-1, 1:-1], g ** N * mode, rtol=0, atol=2e-14)
+    # ghosts and corners are the interior n cells away
+    assert np.array_equal(out[0, 1:-1], out[n, 1:-1]) and np.array_equal(out[n + 1, 1:-1], out[1, 1:-1])
+    assert np.array_equal(out[1:-1, 0], out[1:-1, n]) and np.array_equal(out[1:-1, n + 1], out[1:-1, 1])
+    assert out[0, 0] == out[n, n] and out[0, n + 1] == out[n, 1]
+    assert out[n + 1, 0] == out[1, n] and out[n + 1, n + 1] == out[1, 1]
+
+
+def test_periodic_checkerboard_factor_is_one_minus_two_omega():
+    """(p, q) = (n/2, n/2): the checkerboard, damped by 1 - 2 omega = -1/3 per sweep."""
+    n, N = 12, 7
+    h, lam = lam_of(n)
+    i = np.arange(1, n + 1)[:, None]
+    j = np.arange(1, n + 1)[None, :]
+    board = (-1.0) ** (i + j)
+    out, _, _ = oracle.relax(W.embed(board, n, n + 2), np.zeros((n, n)), n, h, lam, N,
+                             bc=oracle.BC_PERIODIC, resmode=oracle.RES_NONE)
+    np.testing.assert_allclose(out[1:-1, 1:-1], (1 - 2 * OMEGA) ** N * board, rtol=0, atol=1e-15)
+
+
+def test_periodic_sweeps_match_dense_circulant_iteration():
+    n, N = 7, 20
+    h, lam = lam_of(n)
+    f = W.uniform_rhs(n, 71)
+    phi0 = W.uniform_phi(n, 72)
+    out, mx, sq = oracle.relax(phi0, f, n, h, lam, N, bc=oracle.BC_PERIODIC)
+    A = torus_laplacian(n, h)
+    x = phi0[1:-1, 1:-1].ravel().copy()
+    for _ in range(N):
+        x = x + lam * (A @ x) - lam * f.ravel()
+    assert np.abs(out[1:-1, 1:-1].ravel() - x).max() <= 1e-13 * np.abs(x).max()
+    r = f.ravel() - A @ x
+    assert mx == pytest.approx(np.abs(r).max(), rel=1e-10)
+    assert sq == pytest.approx(np.sum(r * r), rel=1e-10)
+    r_or, mx2, _ = oracle.residual(out, f, n, h, bc=oracle.BC_PERIODIC)
+    assert np.abs(r_or.ravel() - r).max() <= 1e-10 * np.abs(r).max()
+
+
+def test_periodic_constant_is_fixed_and_mean_moves_by_lambda_mean_f():
+    """S of a constant is exactly 0 on a torus, so a constant is a fixed point for f = 0;
+    and sum(S phi) = 0, so each sweep lowers the sum of phi by lambda * sum(f) (up to
+    rounding)."""
+    n = 20
+    h, lam = lam_of(n)
+    c = np.full((n + 2, n + 2), 0.625)
+    out, _, _ = oracle.relax(c, np.zeros((n, n)), n, h, lam, 9, bc=oracle.BC_PERIODIC,
+                             resmode=oracle.RES_NONE)
+    assert np.all(out == 0.625)
+    f = W.uniform_rhs(n, 73)
+    phi0 = W.uniform_phi(n, 74)
+    N = 15
+    out, _, _ = oracle.relax(phi0, f, n, h, lam, N, bc=oracle.BC_PERIODIC, resmode=oracle.RES_NONE)
+    expect = phi0[1:-1, 1:-1].sum() - N * lam * f.sum()
+    assert out[1:-1, 1:-1].sum() == pytest.approx(expect, abs=1e-12 * n * n)
+
+
+def test_periodic_stencil_of_mode_is_its_eigenvalue():
+    n, p, q = 24, 5, 2
+    h = 1.0 / n
+    mode = periodic_mode(n, p, q)
+    s = oracle.apply_stencil(W.embed(mode, n, n + 2), n, bc=oracle.BC_PERIODIC)
+    ev = -4.0 * (np.sin(np.pi * p / n) ** 2 + np.sin(np.pi * q / n) ** 2)
+    # the mode's samples carry the rounding of cos at arguments up to ~40: a few 1e-15
+    # each, times the stencil's weights (sum 8)
+    np.testing.assert_allclose(s, ev * mode, rtol=0, atol=1e-13)
