@@ -75,7 +75,16 @@ typedef enum px_status {
 } px_status;
 
 typedef enum px_dtype { PX_F64 = 0, PX_F32 = 1, PX_BF16 = 2 } px_dtype;
-typedef enum px_bc { PX_BC_DIRICHLET0 = 0, PX_BC_GHOST_FIXED = 1 } px_bc;
+typedef enum px_bc {
+    PX_BC_DIRICHLET0 = 0,  /* homogeneous Dirichlet at the cell faces: odd reflection,
+                              ghost := -(adjacent interior) at every sweep             */
+    PX_BC_GHOST_FIXED = 1, /* the ghost ring is read as given and never changed       */
+    PX_BC_PERIODIC = 2     /* torus (Proto's own boundary, Section II): a ghost is the
+                              interior cell n cells away; outputs write the ghost ring
+                              and its corners.  Stencil, residual, relaxation, autotune
+                              and plain solves only (PX_EUNSUPPORTED elsewhere); a
+                              solvable system needs f with zero sum                     */
+} px_bc;
 typedef enum px_resmode {
     PX_RES_NONE = 0,   /* no norms                                              */
     PX_RES_LAGGED = 1, /* norms of the residual of the LAST sweep's input, the  */

@@ -28,7 +28,7 @@ OK, EINVAL, EUNSUPPORTED, EALIAS, EHIP, ENOTCONV, EDIVERGED, ENONFINITE, ENOMEM 
 STATUS_NAMES = {0: "PX_OK", -1: "PX_EINVAL", -2: "PX_EUNSUPPORTED", -3: "PX_EALIAS", -4: "PX_EHIP",
                 -5: "PX_ENOTCONV", -6: "PX_EDIVERGED", -7: "PX_ENONFINITE", -8: "PX_ENOMEM"}
 F64, F32, BF16 = 0, 1, 2
-BC_DIRICHLET0, BC_GHOST_FIXED = 0, 1
+BC_DIRICHLET0, BC_GHOST_FIXED, BC_PERIODIC = 0, 1, 2
 RES_NONE, RES_LAGGED, RES_FINAL = 0, 1, 2
 SOLVE_PLAIN, SOLVE_MIXED_F32, SOLVE_MIXED_BF16 = 0, 1, 2
 LAPLACE_TAPS = (0.0, 1.0, 0.0, 1.0, -4.0, 1.0, 0.0, 1.0, 0.0)

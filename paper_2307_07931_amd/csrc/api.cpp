@@ -73,7 +73,7 @@ int hip_fail(hipError_t e, const char *what)
 constexpr int MAX_N = 1 << 17;
 
 bool valid_dtype(int d) { return d == F64 || d == F32 || d == BF16; }
-bool valid_bc(int b) { return b == DIRICHLET0 || b == GHOST_FIXED; }
+bool valid_bc(int b) { return b == DIRICHLET0 || b == GHOST_FIXED || b == PERIODIC; }
 
 size_t grid_bytes(int n, int ld, int dtype) { return (size_t)(n + 2) * (size_t)ld * elem_size(dtype); }
 size_t flat_bytes(int n, int ld, int dtype) { return (size_t)n * (size_t)ld * elem_size(dtype); }
@@ -559,6 +559,8 @@ int px_solve(void *phi, int n, int ld, int dtype, const void *f, int ld_f, doubl
     if (o->max_sweeps < 0) return fail(PX_EINVAL, "max_sweeps < 0");
     if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
     if (!valid_bc(o->bc)) return fail(PX_EINVAL, "unknown bc %d", o->bc);
+    if (o->bc == PERIODIC && o->mode != PX_SOLVE_PLAIN)
+        return fail(PX_EUNSUPPORTED, "mixed-precision refinement takes the Dirichlet and fixed-ghost boundaries");
     const int check_every = o->check_every > 0 ? o->check_every : 100;
     const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : default_inner(o->mode);
     const size_t gb = grid_bytes(n, ld, dtype);
@@ -765,6 +767,7 @@ int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps,
     if (nsweeps < 1) return fail(PX_EINVAL, "nsweeps = %d < 1", nsweeps);
     if (tblock < 0 || tblock > 8) return fail(PX_EINVAL, "tblock = %d outside [0, 8]", tblock);
     if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (bc == PERIODIC) return fail(PX_EUNSUPPORTED, "batches take the Dirichlet and fixed-ghost boundaries");
     if (resmode < RES_NONE || resmode > RES_FINAL) return fail(PX_EINVAL, "unknown resmode %d", resmode);
     if (resmode == RES_LAGGED) return fail(PX_EUNSUPPORTED, "batched relaxation reports FINAL norms only");
     if (resmode == RES_FINAL && !norms) return fail(PX_EINVAL, "norms is NULL");
@@ -785,6 +788,7 @@ int px_autotune_batched(const px_problem *probs, int nprob, int dtype, int bc, p
     int st = check_batch(probs, nprob, dtype, bp);
     if (st) return st;
     if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (bc == PERIODIC) return fail(PX_EUNSUPPORTED, "batches take the Dirichlet and fixed-ghost boundaries");
     if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
     if ((st = set_device(ctx))) return st;
     if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
@@ -810,6 +814,7 @@ int px_solve_batched(const px_problem *probs, int nprob, const px_solve_opts *o,
     if (o->max_sweeps < 0) return fail(PX_EINVAL, "max_sweeps < 0");
     if (o->tblock < 0 || o->tblock > 8) return fail(PX_EINVAL, "tblock outside [0, 8]");
     if (!valid_bc(o->bc)) return fail(PX_EINVAL, "unknown bc %d", o->bc);
+    if (o->bc == PERIODIC) return fail(PX_EUNSUPPORTED, "batches take the Dirichlet and fixed-ghost boundaries");
     const int inner = o->inner_sweeps > 0 ? o->inner_sweeps : default_inner(o->mode);
     if ((st = set_device(ctx))) return st;
     if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();

@@ -54,21 +54,30 @@ __device__ __forceinline__ unsigned long long abs_bits(double x)
 
 // Neighbour fetch of phi at (i, j) honouring the boundary mode; (ci, cj) is the
 // interior cell the neighbour belongs to, C its value.
+// Boundary modes of these per-cell kernels: DIRICHLET0 (odd reflection), GHOST_FIXED (the
+// ghost as stored), PERIODIC (the interior cell n cells away).
+__device__ __forceinline__ int wrap_index(int i, int n) { return i == 0 ? n : (i == n + 1 ? 1 : i); }
+
 template <typename T>
 __device__ __forceinline__ typename Elem<T>::A nb(const T *__restrict__ phi, int ld, int n, int i,
-                                                  int j, typename Elem<T>::A C, bool dir)
+                                                  int j, typename Elem<T>::A C, int bc)
 {
-    if (dir && (i == 0 || i == n + 1 || j == 0 || j == n + 1)) return -C;
+    if (bc == DIRICHLET0 && (i == 0 || i == n + 1 || j == 0 || j == n + 1)) return -C;
+    if (bc == PERIODIC) {
+        i = wrap_index(i, n);
+        j = wrap_index(j, n);
+    }
     return Elem<T>::load(phi[(size_t)i * ld + j]);
 }
 
 // Corner ghost under DIRICHLET0 (general taps only): +(diagonal interior).
 template <typename T>
 __device__ __forceinline__ typename Elem<T>::A at_reflected(const T *__restrict__ phi, int ld,
-                                                            int n, int i, int j, bool dir)
+                                                            int n, int i, int j, int bc)
 {
     using A = typename Elem<T>::A;
-    if (!dir) return Elem<T>::load(phi[(size_t)i * ld + j]);
+    if (bc == PERIODIC) return Elem<T>::load(phi[(size_t)wrap_index(i, n) * ld + wrap_index(j, n)]);
+    if (bc != DIRICHLET0) return Elem<T>::load(phi[(size_t)i * ld + j]);
     int ii = i, jj = j;
     A sgn = 1;
     if (ii == 0) { ii = 1; sgn = -sgn; }
@@ -81,14 +90,14 @@ __device__ __forceinline__ typename Elem<T>::A at_reflected(const T *__restrict_
 
 template <typename T>
 __device__ __forceinline__ typename Elem<T>::A lap5(const T *__restrict__ phi, int ld, int n, int i,
-                                                    int j, bool dir, typename Elem<T>::A &C)
+                                                    int j, int bc, typename Elem<T>::A &C)
 {
     using A = typename Elem<T>::A;
     C = Elem<T>::load(phi[(size_t)i * ld + j]);
-    const A N = nb<T>(phi, ld, n, i - 1, j, C, dir);
-    const A W = nb<T>(phi, ld, n, i, j - 1, C, dir);
-    const A E = nb<T>(phi, ld, n, i, j + 1, C, dir);
-    const A S = nb<T>(phi, ld, n, i + 1, j, C, dir);
+    const A N = nb<T>(phi, ld, n, i - 1, j, C, bc);
+    const A W = nb<T>(phi, ld, n, i, j - 1, C, bc);
+    const A E = nb<T>(phi, ld, n, i, j + 1, C, bc);
+    const A S = nb<T>(phi, ld, n, i + 1, j, C, bc);
     return (((N - (A)4 * C) + W) + E) + S;
 }
 
@@ -105,11 +114,10 @@ __global__ __launch_bounds__(BX) void stencil_kernel(const T *__restrict__ phi, 
     const int j = blockIdx.x * BX + threadIdx.x + 1;
     const int i = blockIdx.y + 1;
     if (j > n) return;
-    const bool dir = (bc == DIRICHLET0);
     A acc;
     if (LAP) {
         A C;
-        acc = lap5<T>(phi, ld, n, i, j, dir, C);
+        acc = lap5<T>(phi, ld, n, i, j, bc, C);
     } else {
         // visiting order (-1,0), (0,0), (0,-1), (0,1), (1,0), corners; zero taps skipped
         const int di[9] = {-1, 0, 0, 0, 1, -1, -1, 1, 1};
@@ -120,7 +128,7 @@ __global__ __launch_bounds__(BX) void stencil_kernel(const T *__restrict__ phi, 
         for (int k = 0; k < 9; ++k) {
             const A tap = (A)taps.t[(di[k] + 1) * 3 + (dj[k] + 1)];
             if (tap == (A)0) continue;
-            const A term = tap * at_reflected<T>(phi, ld, n, i + di[k], j + dj[k], dir);
+            const A term = tap * at_reflected<T>(phi, ld, n, i + di[k], j + dj[k], bc);
             acc = first ? term : acc + term;
             first = false;
         }
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(BX) void residual_kernel(const T *__restrict__ phi,
     double sm = 0.0;
     if (j <= n) {
         A C;
-        const A s = lap5<T>(phi, ld, n, i, j, bc == DIRICHLET0, C);
+        const A s = lap5<T>(phi, ld, n, i, j, bc, C);
         const A rr = Elem<T>::load(f[(size_t)(i - 1) * ld_f + (j - 1)]) - (A)c * s;
         if (r) r[(size_t)(i - 1) * ld_r + (j - 1)] = Elem<T>::store(rr);
         const double rd = (double)rr;

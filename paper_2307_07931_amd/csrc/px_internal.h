@@ -15,7 +15,7 @@ struct px_net;
 namespace px {
 
 enum Dtype { F64 = 0, F32 = 1, BF16 = 2 };
-enum Bc { DIRICHLET0 = 0, GHOST_FIXED = 1 };
+enum Bc { DIRICHLET0 = 0, GHOST_FIXED = 1, PERIODIC = 2 };
 enum ResMode { RES_NONE = 0, RES_LAGGED = 1, RES_FINAL = 2 };
 
 struct bf16 {

@@ -47,7 +47,7 @@ static void set_launch_order(KArgs &ka, const Geometry &g, int V, int n, int NL,
     int txl = -1, txr = -1, tyt = -1, tyb = -1;
     for (int tx = 0; tx < g.tiles_x; ++tx) {
         const int c0 = g.col_origin + tx * g.stride - g.halo;
-        if (c0 >= 1 && c0 + WAVE * V - 1 <= n) {
+        if (c0 >= 1 && c0 + WAVE * V - (NL == 1 ? 0 : 1) <= n) {  // the predicate of relax_one_tile
             if (txl < 0) txl = tx;
             txr = tx + 1;
         }

@@ -148,6 +148,17 @@ template <int V> struct Io<double, V, true> {
     {
         return Raw{__builtin_amdgcn_raw_buffer_load_b128(r, col0 * 8, 0, 0)};
     }
+    __device__ static Raw load_cols(__amdgpu_buffer_rsrc_t r, const int (&col)[V])
+    {
+        const u32x2 a = __builtin_amdgcn_raw_buffer_load_b64(r, col[0] * 8, 0, 0);
+        const u32x2 b = __builtin_amdgcn_raw_buffer_load_b64(r, col[1] * 8, 0, 0);
+        u32x4 u;
+        u.x = a.x;
+        u.y = a.y;
+        u.z = b.x;
+        u.w = b.y;
+        return Raw{u};
+    }
     __device__ static void unpack(const Raw &x, A (&d)[V])
     {
         d[0] = __hiloint2double((int)x.u.y, (int)x.u.x);
@@ -177,6 +188,13 @@ template <int V> struct Io<double, V, false> {
         for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b64(r, (col0 + v) * 8, 0, 0);
         return x;
     }
+    __device__ static Raw load_cols(__amdgpu_buffer_rsrc_t r, const int (&col)[V])
+    {
+        Raw x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b64(r, col[v] * 8, 0, 0);
+        return x;
+    }
     __device__ static void unpack(const Raw &x, A (&d)[V])
     {
 #pragma unroll
@@ -190,6 +208,15 @@ template <int V> struct Io<float, V, true> {
     __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
     {
         return Raw{__builtin_amdgcn_raw_buffer_load_b128(r, col0 * 4, 0, 0)};
+    }
+    __device__ static Raw load_cols(__amdgpu_buffer_rsrc_t r, const int (&col)[V])
+    {
+        u32x4 u;
+        u.x = __builtin_amdgcn_raw_buffer_load_b32(r, col[0] * 4, 0, 0);
+        u.y = __builtin_amdgcn_raw_buffer_load_b32(r, col[1] * 4, 0, 0);
+        u.z = __builtin_amdgcn_raw_buffer_load_b32(r, col[2] * 4, 0, 0);
+        u.w = __builtin_amdgcn_raw_buffer_load_b32(r, col[3] * 4, 0, 0);
+        return Raw{u};
     }
     __device__ static void unpack(const Raw &x, A (&d)[V])
     {
@@ -222,6 +249,13 @@ template <int V> struct Io<float, V, false> {
         for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b32(r, (col0 + v) * 4, 0, 0);
         return x;
     }
+    __device__ static Raw load_cols(__amdgpu_buffer_rsrc_t r, const int (&col)[V])
+    {
+        Raw x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b32(r, col[v] * 4, 0, 0);
+        return x;
+    }
     __device__ static void unpack(const Raw &x, A (&d)[V])
     {
 #pragma unroll
@@ -235,6 +269,16 @@ template <int V> struct Io<bf16, V, true> {
     __device__ static Raw load(__amdgpu_buffer_rsrc_t r, int col0)
     {
         return Raw{__builtin_amdgcn_raw_buffer_load_b64(r, col0 * 2, 0, 0)};
+    }
+    __device__ static Raw load_cols(__amdgpu_buffer_rsrc_t r, const int (&col)[V])
+    {
+        unsigned e[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) e[v] = (unsigned)__builtin_amdgcn_raw_buffer_load_b16(r, col[v] * 2, 0, 0);
+        u32x2 u;
+        u.x = e[0] | (e[1] << 16);
+        u.y = e[2] | (e[3] << 16);
+        return Raw{u};
     }
     __device__ static void unpack(const Raw &x, A (&d)[V])
     {
@@ -263,6 +307,13 @@ template <int V> struct Io<bf16, V, false> {
         Raw x;
 #pragma unroll
         for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b16(r, (col0 + v) * 2, 0, 0);
+        return x;
+    }
+    __device__ static Raw load_cols(__amdgpu_buffer_rsrc_t r, const int (&col)[V])
+    {
+        Raw x;
+#pragma unroll
+        for (int v = 0; v < V; ++v) x.u[v] = __builtin_amdgcn_raw_buffer_load_b16(r, col[v] * 2, 0, 0);
         return x;
     }
     __device__ static void unpack(const Raw &x, A (&d)[V])
@@ -344,6 +395,15 @@ __device__ __forceinline__ void store_cols(__amdgpu_buffer_rsrc_t r, int col0, i
     for (int v = 0; v < V; ++v) Store1<T>::st(r, col0 + v, col0 + v >= lo && col0 + v < hi, x[v]);
 }
 
+// Periodic grids: row or column x of the ghosted index space (any x, ghosts and halo
+// included) as the interior cell of the torus it stands for, in [1, n].
+__device__ __forceinline__ int torus(int x, int n)
+{
+    int r = (x - 1) % n;
+    if (r < 0) r += n;
+    return r + 1;
+}
+
 // Geometry of one wave's tile (wave-uniform except mc).
 struct Tile {
     int n, oc0, oc1, mc, y0, y1;
@@ -374,11 +434,16 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
     const int n = tl.n, oc0 = tl.oc0, oc1 = tl.oc1, mc = tl.mc, y0 = tl.y0, y1 = tl.y1;
     const int lane = threadIdx.x & (WAVE - 1);
     const int c0 = mc - lane * V;
-    const int ecol = (lane == 0) ? (c0 >= 1 ? c0 - 1 : OOB) : (lane == WAVE - 1 ? c0 + WAVE * V : OOB);
-    // f is compact: f column j - 1 belongs to phi column j
-    const int efcol = (VEC && lane == 0 && c0 >= 1) ? c0 - 1 : OOB;
     const bool whole = tl.whole;
     const bool dir = (p.bc == DIRICHLET0);
+    // periodic grid (edge tiles only: an interior tile never reaches the ghost ring): rows
+    // and columns of every load wrap onto the torus, and every cell is computed and
+    // stored, the ghost ring and its corners included, so no boundary substitution
+    const bool per = EDGE && p.bc == PERIODIC;
+    const int ecol = per ? (lane == 0 ? torus(c0 - 1, n) : (lane == WAVE - 1 ? torus(c0 + WAVE * V, n) : OOB))
+                         : ((lane == 0) ? (c0 >= 1 ? c0 - 1 : OOB) : (lane == WAVE - 1 ? c0 + WAVE * V : OOB));
+    // f is compact: f column j - 1 belongs to phi column j
+    const int efcol = (VEC && lane == 0) ? (per ? torus(c0, n) - 1 : (c0 >= 1 ? c0 - 1 : OOB)) : OOB;
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
     const A w = (A)p.w, cc = (A)p.c, lam = (A)p.lam;
 
@@ -401,6 +466,27 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
     // columns of f loaded by this lane: its own aligned columns (VEC, shifted by one
     // lane afterwards) or exactly the columns its cells need
     const int fc = VEC ? mc : mc - 1;
+    // the loads of one row of phi and f (and the strip's outer neighbours), wrapped on a torus
+    int pcol[V], fcol[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        pcol[v] = per ? torus(mc + v, n) : 0;
+        fcol[v] = per ? torus(fc + v + 1, n) - 1 : 0;
+    }
+    auto load_phi = [&](int row) -> Raw {
+        if (per) return IO::load_cols(row_rsrc(p.in, torus(row, n), n + 2, rb), pcol);
+        return IO::load(row_rsrc(p.in, row, n + 2, rb), mc);
+    };
+    auto load_f = [&](int row) -> Raw {  // f of phi row `row`
+        if (per) return IO::load_cols(row_rsrc(p.f, torus(row, n) - 1, n, rbf), fcol);
+        return IO::load(row_rsrc(p.f, row - 1, n, rbf), fc);
+    };
+    auto load1_phi = [&](int row) -> A {
+        return Load1<T>::ld(row_rsrc(p.in, per ? torus(row, n) : row, n + 2, rb), ecol);
+    };
+    auto load1_f = [&](int row) -> A {
+        return Load1<T>::ld(row_rsrc(p.f, (per ? torus(row, n) : row) - 1, n, rbf), efcol);
+    };
 
     // Rows are prefetched PF ahead into a ring of raw registers; the loop is
     // unrolled PF times so the ring rotates by renaming, never by moves that would
@@ -413,11 +499,11 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
     A ex1 = 0, ex2 = 0;                    // single elements of rows s - 1, s
 #pragma unroll
     for (int q = 0; q < PF; ++q) {
-        pf[q] = IO::load(row_rsrc(p.in, sb + q, n + 2, rb), mc);
-        pff[q] = IO::load(row_rsrc(p.f, sb + q - 1, n, rbf), fc);
+        pf[q] = load_phi(sb + q);
+        pff[q] = load_f(sb + q);
         if constexpr (NH) {
-            pe[q] = Load1<T>::ld(row_rsrc(p.in, sb + q, n + 2, rb), ecol);
-            pfe[q] = Load1<T>::ld(row_rsrc(p.f, sb + q - 1, n, rbf), efcol);
+            pe[q] = load1_phi(sb + q);
+            pfe[q] = load1_f(sb + q);
         }
     }
     for (int s0 = sb; s0 < se; s0 += PF) {
@@ -452,11 +538,11 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                     for (int v = 0; v < V; ++v) fq[0][v] = fo[v];
                 }
             }
-            pf[q] = IO::load(row_rsrc(p.in, s + PF, n + 2, rb), mc);
-            pff[q] = IO::load(row_rsrc(p.f, s + PF - 1, n, rbf), fc);
+            pf[q] = load_phi(s + PF);
+            pff[q] = load_f(s + PF);
             if constexpr (NH) {
-                pe[q] = Load1<T>::ld(row_rsrc(p.in, s + PF, n + 2, rb), ecol);
-                pfe[q] = Load1<T>::ld(row_rsrc(p.f, s + PF - 1, n, rbf), efcol);
+                pe[q] = load1_phi(s + PF);
+                pfe[q] = load1_f(s + PF);
             }
 
             // ---- levels 1..NL, level t at row s - t
@@ -496,7 +582,7 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                         const A C = win[t - 1][1][v];
                         const A u = E::round((C + w * st[v]) - lam * fq[t][v]);
                         const bool inter = row_in && col >= 1 && col <= n;
-                        nv[v] = EDGE ? (inter ? u : (dir ? (A)0 : C)) : u;
+                        nv[v] = EDGE ? ((inter || per) ? u : (dir ? (A)0 : C)) : u;
                     }
                     if (t < NL) {
 #pragma unroll
@@ -534,11 +620,13 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                                                           rc1, whole, nv, true);
                             }
                         } else {
-                            const bool ghost_row = (r == 0 || r == n + 1);
-                            const int lo = max(oc0, ghost_row ? 1 : 0);
-                            const int hi = min(oc1, ghost_row ? n + 1 : n + 2);
+                            // fixed ghosts: the ghost ring keeps its values, corners untouched;
+                            // torus: the ghost ring and its corners hold their wrapped cells
+                            const bool skip_corners = (r == 0 || r == n + 1) && !per;
+                            const int lo = max(oc0, skip_corners ? 1 : 0);
+                            const int hi = min(oc1, skip_corners ? n + 1 : n + 2);
                             store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, lo, hi,
-                                                  whole && !ghost_row, nv, false);
+                                                  whole && !skip_corners, nv, false);
                         }
                     }
                 }
@@ -743,8 +831,9 @@ __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lan
     const int y0 = ty * p.rows, y1 = min(y0 + p.rows, n + 2);
     // tiles whose outputs avoid columns 0, 1, n, n+1 store whole vectors
     const bool whole = oc0 >= V && oc1 <= n;
-    // interior tile: loaded columns and needed rows all inside [1, n]
-    const bool interior = c0 >= 1 && c0 + WAVE * V - 1 <= n && y0 - NL >= 1 && y1 + NL - 1 <= n;
+    // interior tile: loaded columns and needed rows all inside [1, n] (with one level the
+    // strip also reads the column right of it, which must not be the ghost column n + 1)
+    const bool interior = c0 >= 1 && c0 + WAVE * V - (NL == 1 ? 0 : 1) <= n && y0 - NL >= 1 && y1 + NL - 1 <= n;
     const Tile tl{n, oc0, oc1, mc, y0, y1, whole};
     if constexpr (RM == RES_NONE && (K + 1) % 3 == 0) {
         const bool up = (ty & 1) != 0;

@@ -131,6 +131,7 @@ def test_solve_validation(ctx):
     assert solve(max_sweeps=-5) == px.EINVAL
     assert solve(tblock=12) == px.EINVAL
     assert solve(bc=3) == px.EINVAL
+    assert solve(bc=px.BC_PERIODIC, mode=px.SOLVE_MIXED_F32) == px.EUNSUPPORTED
     assert L.px_solve(P(FAKE), 8, 10, 0, P(FAKE2), 8, 0.125, 1e-3, None, ctypes.byref(st), ctx,
                       None) == px.EINVAL
 
@@ -187,6 +188,8 @@ def test_batched_validation(ctx):
     assert relax(tblock=9) == px.EINVAL
     assert relax(resmode=2) == px.EINVAL            # FINAL needs norms
     assert relax(resmode=1) == px.EUNSUPPORTED      # lagged norms are not reported for batches
+    assert relax(bc=px.BC_PERIODIC) == px.EUNSUPPORTED
+    assert relax(bc=3) == px.EINVAL
     bad = (px._Problem * 2)(probs[0], px._Problem(FAKE + 8, FAKE2 * 3, 8, 16, 8, 0.125, 1e-3))
     assert relax(probs=bad) == px.EINVAL           # not 16-byte aligned
     over = (px._Problem * 2)(probs[0], px._Problem(FAKE + 256, FAKE2 * 3, 8, 16, 8, 0.125, 1e-3))
