@@ -414,7 +414,7 @@ struct Tile {
 // the wave computes is an interior cell, so no boundary substitution, no ghost writes
 // and no selects on the update -- the common case, taken when the tile's loaded
 // columns and needed rows all lie in [1, n].
-template <typename T, int V, int K, int RM, int PF, bool VEC, bool EDGE>
+template <typename T, int V, int K, int RM, int PF, bool VEC, bool EDGE, bool PER = false>
 __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigned long long &rmax,
                                          double &rsum)
 {
@@ -439,7 +439,7 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
     // periodic grid (edge tiles only: an interior tile never reaches the ghost ring): rows
     // and columns of every load wrap onto the torus, and every cell is computed and
     // stored, the ghost ring and its corners included, so no boundary substitution
-    const bool per = EDGE && p.bc == PERIODIC;
+    constexpr bool per = EDGE && PER;  // a separate instance: no wrap tests in the others
     const int ecol = per ? (lane == 0 ? torus(c0 - 1, n) : (lane == WAVE - 1 ? torus(c0 + WAVE * V, n) : OOB))
                          : ((lane == 0) ? (c0 >= 1 ? c0 - 1 : OOB) : (lane == WAVE - 1 ? c0 + WAVE * V : OOB));
     // f is compact: f column j - 1 belongs to phi column j
@@ -474,11 +474,11 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
         fcol[v] = per ? torus(fc + v + 1, n) - 1 : 0;
     }
     auto load_phi = [&](int row) -> Raw {
-        if (per) return IO::load_cols(row_rsrc(p.in, torus(row, n), n + 2, rb), pcol);
+        if constexpr (per) return IO::load_cols(row_rsrc(p.in, torus(row, n), n + 2, rb), pcol);
         return IO::load(row_rsrc(p.in, row, n + 2, rb), mc);
     };
     auto load_f = [&](int row) -> Raw {  // f of phi row `row`
-        if (per) return IO::load_cols(row_rsrc(p.f, torus(row, n) - 1, n, rbf), fcol);
+        if constexpr (per) return IO::load_cols(row_rsrc(p.f, torus(row, n) - 1, n, rbf), fcol);
         return IO::load(row_rsrc(p.f, row - 1, n, rbf), fc);
     };
     auto load1_phi = [&](int row) -> A {
@@ -854,6 +854,8 @@ __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lan
     }
     if (interior)
         run_tile<T, V, K, RM, PF, VEC, false>(p, tl, rmax, rsum);
+    else if (p.bc == PERIODIC)
+        run_tile<T, V, K, RM, PF, VEC, true, true>(p, tl, rmax, rsum);
     else
         run_tile<T, V, K, RM, PF, VEC, true>(p, tl, rmax, rsum);
 }
