@@ -46,11 +46,11 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
-TRAFFIC_SHA256 = "8a31edb482b552a0e5bc43e185ce7800de29e8cfe041c76483e404e3f58cb680"
+TRAFFIC_SHA256 = "1d7514dbedef5ff0f427df86d2f68a4c26eb3cd1fa95fcb8fe337b3ad7640212"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 29): (180077.01, 131371.21), (8, 38): (170997.22, 131366.95), (8, 47): (163687.92, 131364.99),
-    (1, 20): (160269.04, 131271.62), (1, 47): (147382.53, 131271.46), (1, 64): (141643.23, 131268.78),
+    (8, 29): (179937.47, 131373.57), (8, 38): (171020.59, 131367.15), (8, 47): (163531.86, 131364.90),
+    (1, 20): (160319.43, 131271.62), (1, 47): (147406.73, 131271.33), (1, 64): (141687.24, 131268.72),
 }
 VARIANT_ROWS = (12, 16, 20, 29, 38, 47, 64, 96)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
