@@ -45,7 +45,7 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # 1 GiB device-to-device copy (FETCH_SIZE 524302.64 KiB -> x 1048576 / 524302.64,
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
-TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip")
+TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip", "px_internal.h")
 TRAFFIC_SHA256 = "1d7514dbedef5ff0f427df86d2f68a4c26eb3cd1fa95fcb8fe337b3ad7640212"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch

@@ -54,6 +54,12 @@ template <> struct Elem<bf16> {
     __device__ static A round(A x) { return bf16_to_f32(f32_to_bf16_rne(x)); }
 };
 
+// N - 4C rounded once.  Scaling by 4 is exact while 4|C| stays finite (|C| up to a quarter of
+// the largest finite value), so there the fused form rounds the same exact difference as
+// forming 4C and then subtracting -- the same bits -- in one instruction instead of two.
+__device__ __forceinline__ double sub4(double N, double C) { return __builtin_fma(-4.0, C, N); }
+__device__ __forceinline__ float sub4(float N, float C) { return __builtin_fmaf(-4.0f, C, N); }
+
 inline int elem_size(int dtype) { return dtype == F64 ? 8 : dtype == F32 ? 4 : 2; }
 
 // Per-wave (or per-block) partial norms: max|r| as the bit pattern of a

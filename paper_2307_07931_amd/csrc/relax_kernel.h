@@ -571,7 +571,7 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
                         if (col == 1) Wn = -C;
                         if (col == n) En = -C;
                     }
-                    st[v] = (((N - (A)4 * C) + Wn) + En) + S;
+                    st[v] = ((sub4(N, C) + Wn) + En) + S;
                 }
                 if (t <= K) {
                     A nv[V];
@@ -739,7 +739,7 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
                     Wn = west[v] ? -C : Wn;
                     En = east[v] ? -C : En;
                 }
-                const A st = (((N - (A)4 * C) + Wn) + En) + S;
+                const A st = ((sub4(N, C) + Wn) + En) + S;
                 nv[v] = E::round((C + w * st) - lf[sf][v]);
             }
             if (t < K) {
