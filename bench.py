@@ -46,11 +46,11 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip", "px_internal.h")
-TRAFFIC_SHA256 = "1d7514dbedef5ff0f427df86d2f68a4c26eb3cd1fa95fcb8fe337b3ad7640212"
+TRAFFIC_SHA256 = "a4fd04db9c0add5e80b5a4c60b69d6d9300b967d29b7f279b8f1b4938badafd5"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 29): (179937.47, 131373.57), (8, 38): (171020.59, 131367.15), (8, 47): (163531.86, 131364.90),
-    (1, 20): (160319.43, 131271.62), (1, 47): (147406.73, 131271.33), (1, 64): (141687.24, 131268.72),
+    (8, 29): (180597.76, 131362.20), (8, 38): (171524.62, 131357.16), (8, 47): (163815.00, 131352.77),
+    (1, 20): (160349.88, 131271.69), (1, 47): (147409.70, 131271.46), (1, 64): (141690.27, 131268.59),
 }
 VARIANT_ROWS = (12, 16, 20, 29, 38, 47, 64, 96)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
