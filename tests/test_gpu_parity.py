@@ -304,3 +304,32 @@ def test_periodic_plain_solve_matches_oracle(ctx):
     assert st.rel_res_max <= 1e-6 and st.sweeps % 256 == 0
     ref, _, _ = H.oracle_relax(phi0, f, n, h, lam, st.sweeps, "f64", bc=px.BC_PERIODIC)
     H.assert_grid_bitwise(H.to_storage_np(pd, "f64"), ref, n)
+
+
+@pytest.mark.parametrize("dt,scale,resmode", [
+    ("f64", 1e307, px.RES_NONE), ("f64", 1e-310, px.RES_FINAL),
+    ("f32", 3e37, px.RES_NONE), ("f32", 1e-40, px.RES_FINAL)])
+@pytest.mark.parametrize("k", [1, 8])
+def test_extreme_magnitudes_bitwise(dt, scale, resmode, k):
+    """Both ends of the floating-point range, interior and edge tiles: grids scaled so that the
+    stencil sums reach about half the largest finite value (the kernel forms N - 4C as one
+    fused multiply-add, which equals multiply-then-subtract while 4C stays finite; the
+    residual, scaled by 1/h^2, overflows, so no norms there) and to subnormal magnitudes
+    (gradual underflow on both sides)."""
+    H.require_gpu()
+    n = 333
+    h, lam = params(n)
+    phi0 = W.uniform_phi(n, 700 + k) * scale
+    f = W.uniform_rhs(n, 710 + k) * scale
+    sweeps = 2 * k + 1
+    ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, sweeps, dt, resmode=resmode)
+    c = px.Context()
+    c.set_tile_rows(29)
+    print(f"case: {dt} scale={scale:g} k={k} sweeps={sweeps}", flush=True)
+    got, nm = H.gpu_relax(phi0, f, n, h, lam, sweeps, dt, c, tblock=k, resmode=resmode)
+    c.close()
+    H.assert_grid_bitwise(got, ref, n, what=f"{dt} scale={scale:g} k={k}")
+    interior = np.abs(ref[1:n + 1, 1:n + 1])
+    assert np.isfinite(interior).all() and interior.max() > 0.01 * scale
+    if resmode != px.RES_NONE:
+        H.assert_norms(nm, mx, sq, n=n)
