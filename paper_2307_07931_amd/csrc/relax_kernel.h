@@ -136,6 +136,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void *base, int
                                              RSRC_WORD3);
 }
 
+// A row stream: the address of row `row` of an array, moved one row per step by an add
+// instead of a multiply per row.  The descriptor of a row outside [0, nrows) is zero-sized,
+// as with row_rsrc, so its address is never dereferenced.
+struct RowStream {
+    const char *ptr;
+    int row;
+};
+__device__ __forceinline__ RowStream row_stream(const void *base, int row, int row_bytes)
+{
+    return RowStream{static_cast<const char *>(base) + (long long)row * row_bytes, row};
+}
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const RowStream &s, int nrows, int row_bytes)
+{
+    const bool ok = (unsigned)s.row < (unsigned)nrows;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(s.ptr), (short)0, ok ? row_bytes : 0,
+                                             RSRC_WORD3);
+}
+template <int D> __device__ __forceinline__ void step_stream(RowStream &s, int row_bytes)
+{
+    s.ptr += D > 0 ? (long long)row_bytes : -(long long)row_bytes;
+    s.row += D;
+}
+
 // Raw load / store of V consecutive elements, as one vector access (VEC) or V
 // scalar accesses.  Raw<T,V,VEC> holds the loaded bits until they are consumed.
 template <typename T, int V, bool VEC> struct Io;
@@ -672,7 +695,8 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
                                               typename Elem<T>::A (&win)[K][3][V],
                                               typename Elem<T>::A (&lf)[K + 1][V],
                                               typename Io<T, V, VEC>::Raw (&pf)[3],
-                                              typename Io<T, V, VEC>::Raw (&pff)[3])
+                                              typename Io<T, V, VEC>::Raw (&pff)[3],
+                                              RowStream &sin, RowStream &sfr, RowStream &sout)
 {
     using E = Elem<T>;
     using A = typename E::A;
@@ -712,8 +736,11 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
 #pragma unroll
             for (int v = 0; v < V; ++v) lf[q][v] = lam * fv[v];
         }
-        pf[q % PR] = IO::load(row_rsrc(p.in, x + D * PR, n + 2, rb), mc);
-        pff[q % PR] = IO::load(row_rsrc(p.f, x + D * PR - 1, n, rbf), fc);
+        // rows x + D PR of phi and f (streams sin, sfr); level K stores row x - D K (sout)
+        pf[q % PR] = IO::load(stream_rsrc(sin, n + 2, rb), mc);
+        pff[q % PR] = IO::load(stream_rsrc(sfr, n, rbf), fc);
+        step_stream<D>(sin, rb);
+        step_stream<D>(sfr, rbf);
 #pragma unroll
         for (int t = 1; t <= K; ++t) {
             if (FILLING && s < 2 * t) break;  // rows this level does not need yet
@@ -747,7 +774,7 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
                 for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
             } else if (UP ? r >= y0 : r < y1) {  // the other bound holds once level K runs
                 if constexpr (!EDGE) {
-                    store_cols<T, V, VEC>(row_rsrc(p.out, r, n + 2, rb), mc, oc0, oc1, true, nv, false,
+                    store_cols<T, V, VEC>(stream_rsrc(sout, n + 2, rb), mc, oc0, oc1, true, nv, false,
                                           p.nt_store != 0);
                 } else if (r >= 1 && r <= n) {
                     // interior columns of the row, the ghosts of columns 1 and n, and the
@@ -771,6 +798,7 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
                 }
             }
         }
+        step_stream<D>(sout, rb);
     }
 }
 
@@ -810,10 +838,13 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
         pf[q] = IO::load(row_rsrc(p.in, base + D * q, n + 2, rb), mc);
         pff[q] = IO::load(row_rsrc(p.f, base + D * q - 1, n, rbf), fc);
     }
+    RowStream sin = row_stream(p.in, base + D * PR, rb), sfr = row_stream(p.f, base + D * PR - 1, rbf),
+              sout = row_stream(p.out, base - D * K, rb);
     int s0 = 0;
     for (; s0 < steps && s0 < 2 * K; s0 += U)
-        renamed_block<T, V, K, VEC, true, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff);
-    for (; s0 < steps; s0 += U) renamed_block<T, V, K, VEC, false, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff);
+        renamed_block<T, V, K, VEC, true, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff, sin, sfr, sout);
+    for (; s0 < steps; s0 += U)
+        renamed_block<T, V, K, VEC, false, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff, sin, sfr, sout);
 }
 
 // One wave tile of one problem: geometry, interior/edge dispatch, streaming loop.
