@@ -46,11 +46,13 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip", "px_internal.h")
-TRAFFIC_SHA256 = "a4fd04db9c0add5e80b5a4c60b69d6d9300b967d29b7f279b8f1b4938badafd5"
+TRAFFIC_SHA256 = "ccf5f4744f2a24bff878af30386f9903b997e9cca9883b07d9fa98a2d4eb8183"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 29): (180597.76, 131362.20), (8, 38): (171524.62, 131357.16), (8, 47): (163815.00, 131352.77),
-    (1, 20): (160349.88, 131271.69), (1, 47): (147409.70, 131271.46), (1, 64): (141690.27, 131268.59),
+    (8, 29): (179992.35, 131362.04), (8, 32): (199995.17, 131354.13), (8, 38): (171556.85, 131356.15),
+    (8, 40): (191047.50, 131357.48), (8, 44): (174396.93, 131352.61), (8, 47): (163440.73, 131352.11),
+    (8, 48): (184516.52, 131353.54),
+    (1, 20): (160338.08, 131271.72), (1, 47): (147411.16, 131271.52), (1, 64): (141696.22, 131268.44),
 }
 VARIANT_ROWS = (12, 16, 20, 29, 38, 47, 64, 96)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
