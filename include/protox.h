@@ -37,9 +37,11 @@
  *
  * Element types (px_dtype): FP64, FP32, BF16 (bfloat16 storage, FP32
  * arithmetic, round-to-nearest-even on every store).  Arithmetic follows the
- * association above with no fused multiply-add, so results are reproducible
- * bit for bit; the FP32/BF16 constants w, 1/h^2 and lambda are computed in
- * FP64 and rounded once.
+ * association above with every operation rounded on its own, so results are
+ * reproducible bit for bit (the fused relaxation forms N - 4C as one fused
+ * multiply-add, which rounds the same exact value while 4|C| is finite); the
+ * FP32/BF16 constants w, 1/h^2 and lambda are computed in FP64 and rounded
+ * once.
  *
  * Ownership and ordering: every pointer argument named as device memory is
  * owned by the caller and never freed by the library.  Calls enqueue work on
