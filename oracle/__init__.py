@@ -35,9 +35,9 @@ LAPLACE_TAPS = (0.0, 1.0, 0.0, 1.0, -4.0, 1.0, 0.0, 1.0, 0.0)
 
 
 def build(force: bool = False) -> str:
-    """Compile oracle.c with gcc (plain -O2, no FMA contraction)."""
+    """Compile oracle.c with gcc (plain -O2, no FMA contraction, OpenMP row loops)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
-        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-Wall", "-fPIC",
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-Wall", "-fPIC",
                "-shared", _SRC, "-o", _SO + ".tmp", "-lm"]
         subprocess.check_call(cmd)
         os.replace(_SO + ".tmp", _SO)
@@ -72,8 +72,33 @@ def lib() -> ctypes.CDLL:
         L.ox_bf16_to_f32.restype = ctypes.c_float
         L.ox_f32_to_bf16_array.argtypes = [P, P, ctypes.c_size_t]
         L.ox_f32_to_bf16_array.restype = None
+        L.ox_set_threads.argtypes = [I]
+        L.ox_set_threads.restype = None
+        L.ox_get_threads.restype = I
+        L.ox_max_threads.restype = I
+        L.ox_set_threads(default_threads())
         _lib = L
     return _lib
+
+
+def default_threads() -> int:
+    """Threads for the oracle's row loops: the CPUs this process may run on, at most 16
+    (a GPU machine's share of its host)."""
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        cpus = os.cpu_count() or 1
+    return max(1, min(16, cpus))
+
+
+def set_threads(t: int) -> None:
+    """Threads of the row loops.  Results do not depend on it: the parallel loops write
+    disjoint rows and reduce nothing (the sum of squares stays one sequential loop)."""
+    lib().ox_set_threads(int(t))
+
+
+def get_threads() -> int:
+    return int(lib().ox_get_threads())
 
 
 _SUFFIX = {np.dtype(np.float64): "f64", np.dtype(np.float32): "f32", np.dtype(np.uint16): "bf16"}

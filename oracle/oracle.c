@@ -58,9 +58,20 @@
  * All three follow the same steps; only the storage type changes.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the row loops (OpenMP).  Every parallel loop below writes disjoint
+ * rows and reduces nothing, so results are identical for any thread count; the
+ * one reduction of a sweep (the sum of squares in the norm pass) stays a single
+ * sequential loop in row-major order. */
+static int ox_threads = 1;
+void ox_set_threads(int t) { ox_threads = t > 0 ? t : 1; }
+int ox_get_threads(void) { return ox_threads; }
+int ox_max_threads(void) { return omp_get_num_procs(); }
+#define OX_ROWS _Pragma("omp parallel for schedule(static) num_threads(ox_threads)")
 
 enum { OX_BC_DIRICHLET0 = 0, OX_BC_GHOST_FIXED = 1, OX_BC_PERIODIC = 2 };
 enum { OX_RES_NONE = 0, OX_RES_LAGGED = 1, OX_RES_FINAL = 2 };
@@ -114,10 +125,10 @@ static const int TAP_ORDER[9][2] = {
  * bcs[0..3] = mode of the north (row 0), south (row n+1), west (column 0) and    \
  * east (column n+1) ghost layers.  Corners are reflected only where both        \
  * adjacent sides reflect. */                                                     \
-static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, const int bcs[4])       \
+static void ghosted_fill_##SUF(const ST *phi, int n, int ld, const int bcs[4], AT *w)  \
 {                                                                                    \
     int m = n + 2;                                                                   \
-    AT *w = (AT *)malloc(sizeof(AT) * (size_t)m * m);                                \
+    OX_ROWS                                                                          \
     for (int i = 0; i < m; ++i)                                                      \
         for (int j = 0; j < m; ++j)                                                  \
             w[(size_t)i * m + j] = LOAD(phi[(size_t)i * ld + j]);                    \
@@ -149,6 +160,11 @@ static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, const int bcs[4])   
         w[(size_t)(n + 1) * m + 0] = w[(size_t)n * m + 1];                           \
     if (bcs[1] == OX_BC_DIRICHLET0 && bcs[3] == OX_BC_DIRICHLET0)                    \
         w[(size_t)(n + 1) * m + n + 1] = w[(size_t)n * m + n];                       \
+}                                                                                    \
+static AT *ghosted_copy_##SUF(const ST *phi, int n, int ld, const int bcs[4])       \
+{                                                                                    \
+    AT *w = (AT *)malloc(sizeof(AT) * (size_t)(n + 2) * (n + 2));                    \
+    ghosted_fill_##SUF(phi, n, ld, bcs, w);                                          \
     return w;                                                                        \
 }                                                                                    \
                                                                                      \
@@ -159,6 +175,7 @@ static void stencil_pass_##SUF(const AT *w, int n, const double taps[9], AT *tem
     int m = n + 2;                                                                   \
     AT t[9];                                                                         \
     for (int k = 0; k < 9; ++k) t[k] = (AT)taps[k];                                  \
+    OX_ROWS                                                                          \
     for (int i = 1; i <= n; ++i)                                                     \
         for (int j = 1; j <= n; ++j) {                                               \
             AT acc = 0;                                                              \
@@ -181,6 +198,7 @@ static void stencil_pass_##SUF(const AT *w, int n, const double taps[9], AT *tem
 static void laplace_pass_##SUF(const AT *w, int n, AT *temp)                          \
 {                                                                                    \
     int m = n + 2;                                                                   \
+    OX_ROWS                                                                          \
     for (int i = 1; i <= n; ++i)                                                     \
         for (int j = 1; j <= n; ++j) {                                               \
             AT C = w[(size_t)i * m + j];                                             \
@@ -271,19 +289,19 @@ void ox_residual_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,     
                                                                                      \
 /* One sweep in -> out (the three steps of the algorithm, then the output ghosts). \
  * norms (optional) receives the norm of the residual of the INPUT iterate. */      \
-void ox_sweep_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,         \
-                          int ld_f, double h, double lambda, const int bcs[4],       \
-                          double *norms)                                             \
+static void sweep_work_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,      \
+                             int ld_f, double h, double lambda, const int bcs[4],    \
+                             double *norms, AT *w, AT *temp)                         \
 {                                                                                    \
     AT c = (AT)(1.0 / (h * h));                                                      \
     AT wgt = (AT)(lambda / (h * h));                                                 \
     AT lam = (AT)lambda;                                                             \
     int m = n + 2;                                                                   \
-    AT *w = ghosted_copy_##SUF(in, n, ld, bcs);                                      \
-    AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
+    ghosted_fill_##SUF(in, n, ld, bcs, w);                                           \
     /* (1) Laplacian */                                                              \
     laplace_pass_##SUF(w, n, temp);                                                  \
     /* (2) Jacobi update (1, w, -lambda) on [phi; S phi; rho] */                     \
+    OX_ROWS                                                                          \
     for (int i = 1; i <= n; ++i)                                                     \
         for (int j = 1; j <= n; ++j) {                                               \
             AT p = w[(size_t)i * m + j];                                             \
@@ -294,6 +312,14 @@ void ox_sweep_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,    
     /* (3) max-norm of the input iterate's residual */                               \
     if (norms) norm_pass_##SUF(temp, n, f, ld_f, c, NULL, 0, norms);                 \
     write_out_ghosts_##SUF(in, out, n, ld, bcs);                                     \
+}                                                                                    \
+void ox_sweep_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,         \
+                          int ld_f, double h, double lambda, const int bcs[4],       \
+                          double *norms)                                             \
+{                                                                                    \
+    AT *w = (AT *)malloc(sizeof(AT) * (size_t)(n + 2) * (n + 2));                    \
+    AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
+    sweep_work_##SUF(in, out, n, ld, f, ld_f, h, lambda, bcs, norms, w, temp);       \
     free(temp);                                                                      \
     free(w);                                                                         \
 }                                                                                    \
@@ -321,12 +347,18 @@ void ox_relax_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,    
     ST *b = (ST *)malloc(sizeof(ST) * total);                                        \
     memcpy(a, in, sizeof(ST) * total);                                               \
     memcpy(b, in, sizeof(ST) * total);                                               \
+    /* work arrays of the sweeps, allocated once */                                  \
+    AT *w = (AT *)malloc(sizeof(AT) * (size_t)m * m);                                \
+    AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
     for (int it = 0; it < nsweeps; ++it) {                                           \
         double *nrm = (resmode == OX_RES_LAGGED && it == nsweeps - 1) ? norms : NULL;\
-        ox_sweep_sides_##SUF(a, b, n, ld, f, ld_f, h, lambda, bcs, nrm);             \
+        sweep_work_##SUF(a, b, n, ld, f, ld_f, h, lambda, bcs, nrm, w, temp);        \
         ST *t = a; a = b; b = t;                                                     \
     }                                                                                \
+    free(temp);                                                                      \
+    free(w);                                                                         \
     const int torus = bcs[0] == OX_BC_PERIODIC && bcs[2] == OX_BC_PERIODIC;         \
+    OX_ROWS                                                                          \
     for (int i = 0; i < m; ++i)                                                      \
         for (int j = 0; j < m; ++j) {                                                \
             int corner = (i == 0 || i == m - 1) && (j == 0 || j == m - 1);           \
@@ -384,6 +416,7 @@ int ox_refine(double *phi, int n, int ld, const double *f, int ld_f, double h,
         int converged = norms[0] <= rtol * fmax;
         if (converged || isnan(norms[0]) || outer >= max_outer) break;
         /* r rounded into the inner right-hand side: FP64 -> FP32 (-> BF16) */
+        OX_ROWS
         for (size_t q = 0; q < (size_t)n * n; ++q) {
             if (lowp == 1) ((float *)rl)[q] = (float)r[q];
             else ((uint16_t *)rl)[q] = ox_f32_to_bf16((float)r[q]);
@@ -396,6 +429,7 @@ int ox_refine(double *phi, int n, int ld, const double *f, int ld_f, double h,
         else
             ox_relax_bf16((const uint16_t *)d_in, (uint16_t *)d_out, n, ld,
                           (const uint16_t *)rl, n, h, lambda, k_in, bc, OX_RES_NONE, NULL);
+        OX_ROWS
         for (int i = 1; i <= n; ++i)
             for (int j = 1; j <= n; ++j) {
                 size_t q = (size_t)i * ld + j;

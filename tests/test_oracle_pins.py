@@ -85,6 +85,48 @@ def test_stencil_matches_paper_index_map_and_order():
     assert all((m * (i // n + 1) + (i % n + 1)) == m * (i // n) + i % n + c0 for i in range(n * n))
 
 
+@pytest.mark.parametrize("dt", [np.float64, np.float32])
+@pytest.mark.parametrize("bc", [oracle.BC_DIRICHLET0, oracle.BC_GHOST_FIXED, oracle.BC_PERIODIC])
+def test_residual_and_sweep_use_the_pinned_stencil(dt, bc):
+    """The Laplacian pass behind every residual and sweep is the generic stencil pass of
+    the test above (pinned to Fig. 5's index map and order), bit for bit: the residual is
+    r = f - c S(phi) and the sweep is phi' = (phi + w S(phi)) - lambda f with S from
+    apply_stencil, each operation rounded on its own in the storage precision."""
+    n = 37
+    h, lam = lam_of(n)
+    phi = W.rng(21).uniform(-1, 1, size=(n + 2, n + 2)).astype(dt)
+    f = W.rng(22).uniform(-1, 1, size=(n, n)).astype(dt)
+    S = oracle.apply_stencil(phi, n, bc=bc)
+    c = dt(1.0 / (h * h))
+    w = dt(lam / (h * h))
+    r, _, _ = oracle.residual(phi, f, n, h, bc=bc)
+    assert np.array_equal(r.view(np.uint8), (f - c * S).view(np.uint8))
+    out, _, _ = oracle.sweep(phi, f, n, h, lam, bc=bc)
+    C = phi[1:n + 1, 1:n + 1]
+    upd = (C + w * S) - dt(lam) * f
+    assert np.array_equal(out[1:n + 1, 1:n + 1].view(np.uint8), upd.view(np.uint8))
+
+
+def test_threads_do_not_change_results():
+    """The oracle's row loops run on several threads; every output, the sum of squares
+    included, is the same bit for bit at any thread count."""
+    n, N = 131, 9
+    h, lam = lam_of(n)
+    f = W.uniform_rhs(n, 23)
+    phi0 = W.uniform_phi(n, 24)
+    keep = oracle.get_threads()
+    try:
+        res = []
+        for t in (1, 3, 8):
+            oracle.set_threads(t)
+            res.append(oracle.relax(phi0, f, n, h, lam, N))
+        for out, mx, sq in res[1:]:
+            assert np.array_equal(out.view(np.int64), res[0][0].view(np.int64))
+            assert (mx, sq) == (res[0][1], res[0][2])
+    finally:
+        oracle.set_threads(keep)
+
+
 # ------------------------------------------------------ eigen-structure --
 
 @pytest.mark.parametrize("p,q", [(1, 1), (2, 3), (7, 1), (16, 16), (31, 5), (32, 32)])
