@@ -59,10 +59,11 @@ def lib() -> ctypes.CDLL:
         for suf in ("f64", "f32", "bf16"):
             getattr(L, f"ox_apply_stencil_{suf}").argtypes = [P, I, I, P, D, I, P, I]
             getattr(L, f"ox_residual_{suf}").argtypes = [P, I, I, P, I, D, I, P, I, P]
+            getattr(L, f"ox_residual_terms_{suf}").argtypes = [P, I, I, P, I, D, I, P, P]
             getattr(L, f"ox_sweep_{suf}").argtypes = [P, P, I, I, P, I, D, D, I, P]
             getattr(L, f"ox_relax_{suf}").argtypes = [P, P, I, I, P, I, D, D, I, I, I, P]
             getattr(L, f"ox_relax_sides_{suf}").argtypes = [P, P, I, I, P, I, D, D, I, P, I, P]
-            for nm in ("apply_stencil", "residual", "sweep", "relax", "relax_sides"):
+            for nm in ("apply_stencil", "residual", "residual_terms", "sweep", "relax", "relax_sides"):
                 getattr(L, f"ox_{nm}_{suf}").restype = None
         L.ox_refine.argtypes = [P, I, I, P, I, D, D, I, I, I, I, D, P]
         L.ox_refine.restype = I
@@ -146,6 +147,29 @@ def residual(phi, f, n, h, bc=BC_DIRICHLET0, want_r=True):
         _ptr(phi), n, phi.shape[1], _ptr(f), f.shape[1], float(h), bc,
         _ptr(r) if want_r else None, n, _ptr(norms))
     return r, float(norms[0]), float(norms[1])
+
+
+def residual_terms(phi, f, n, h, bc=BC_DIRICHLET0):
+    """The residual r = f - (1/h^2) S(phi) of every interior cell as the FP64 number
+    whose square the norm adds (the arithmetic type's value, before rounding to
+    storage); returns (rd (n x n float64), max|r|, sum r^2)."""
+    _check_phi(phi, n)
+    _check_f(f, n)
+    assert f.dtype == phi.dtype
+    norms = np.zeros(2, dtype=np.float64)
+    rd = np.zeros((n, n), dtype=np.float64)
+    getattr(lib(), f"ox_residual_terms_{_suffix(phi)}")(
+        _ptr(phi), n, phi.shape[1], _ptr(f), f.shape[1], float(h), bc, _ptr(rd), _ptr(norms))
+    return rd, float(norms[0]), float(norms[1])
+
+
+def exact_sum_squares(rd: np.ndarray) -> float:
+    """The sum of the FP64 squares rd*rd (each rounded once, as the norm forms them),
+    added exactly and rounded once (math.fsum): the reference against which a sum of
+    the same terms in any order is bounded by its own summation depth."""
+    import math
+    rd = np.asarray(rd, dtype=np.float64)
+    return math.fsum((rd * rd).ravel().tolist())
 
 
 def sweep(phi, f, n, h, lam, bc=BC_DIRICHLET0):

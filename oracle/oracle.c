@@ -209,9 +209,10 @@ static void laplace_pass_##SUF(const AT *w, int n, AT *temp)                    
 }                                                                                    \
                                                                                      \
 /* Step 3 (OL max-norm): r = f - c*s over the interior; norms[0] = max|r| (NaN      \
- * propagating), norms[1] = sum r^2 in FP64, row-major order.  r_out optional. */    \
+ * propagating), norms[1] = sum r^2 in FP64, row-major order.  r_out optional;      \
+ * rd_out (optional, n x n) receives each r as the FP64 number the norm squares.  */ \
 static void norm_pass_##SUF(const AT *temp, int n, const ST *f, int ld_f, AT c,      \
-                            ST *r_out, int ld_r, double *norms)                      \
+                            ST *r_out, int ld_r, double *rd_out, double *norms)      \
 {                                                                                    \
     double mx = 0.0, sq = 0.0;                                                       \
     for (int i = 0; i < n; ++i)                                                      \
@@ -219,6 +220,7 @@ static void norm_pass_##SUF(const AT *temp, int n, const ST *f, int ld_f, AT c, 
             AT r = LOAD(f[(size_t)i * ld_f + j]) - c * temp[(size_t)i * n + j];      \
             if (r_out) r_out[(size_t)i * ld_r + j] = STORE(r);                       \
             double rd = (double)r;                                                   \
+            if (rd_out) rd_out[(size_t)i * n + j] = rd;                              \
             mx = nanmax_d(mx, fabs(rd));                                             \
             sq += rd * rd;                                                           \
         }                                                                            \
@@ -268,23 +270,38 @@ void ox_apply_stencil_##SUF(const ST *phi, int n, int ld, const double taps[9], 
 }                                                                                    \
                                                                                      \
 /* Residual of phi: r = f - (1/h^2) S(phi); norms of r; r_out optional. */          \
-void ox_residual_sides_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,    \
-                             double h, const int bcs[4], ST *r_out, int ld_r,        \
-                             double *norms)                                          \
+static void residual_work_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,  \
+                                double h, const int bcs[4], ST *r_out, int ld_r,     \
+                                double *rd_out, double *norms)                       \
 {                                                                                    \
     AT c = (AT)(1.0 / (h * h));                                                      \
     AT *w = ghosted_copy_##SUF(phi, n, ld, bcs);                                     \
     AT *temp = (AT *)malloc(sizeof(AT) * (size_t)n * n);                             \
     laplace_pass_##SUF(w, n, temp);                                                  \
-    norm_pass_##SUF(temp, n, f, ld_f, c, r_out, ld_r, norms);                        \
+    norm_pass_##SUF(temp, n, f, ld_f, c, r_out, ld_r, rd_out, norms);                \
     free(temp);                                                                      \
     free(w);                                                                         \
+}                                                                                    \
+void ox_residual_sides_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,    \
+                             double h, const int bcs[4], ST *r_out, int ld_r,        \
+                             double *norms)                                          \
+{                                                                                    \
+    residual_work_##SUF(phi, n, ld, f, ld_f, h, bcs, r_out, ld_r, NULL, norms);      \
 }                                                                                    \
 void ox_residual_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,          \
                        double h, int bc, ST *r_out, int ld_r, double *norms)         \
 {                                                                                    \
     const int bcs[4] = {bc, bc, bc, bc};                                             \
     ox_residual_sides_##SUF(phi, n, ld, f, ld_f, h, bcs, r_out, ld_r, norms);        \
+}                                                                                    \
+/* The residual of every interior cell as the FP64 number whose square the norm     \
+ * adds (the arithmetic type's value, before any rounding to storage): rd_out is    \
+ * n x n compact.  For an exact reference of the sum of squares. */                  \
+void ox_residual_terms_##SUF(const ST *phi, int n, int ld, const ST *f, int ld_f,    \
+                             double h, int bc, double *rd_out, double *norms)        \
+{                                                                                    \
+    const int bcs[4] = {bc, bc, bc, bc};                                             \
+    residual_work_##SUF(phi, n, ld, f, ld_f, h, bcs, NULL, 0, rd_out, norms);        \
 }                                                                                    \
                                                                                      \
 /* One sweep in -> out (the three steps of the algorithm, then the output ghosts). \
@@ -310,7 +327,7 @@ static void sweep_work_##SUF(const ST *in, ST *out, int n, int ld, const ST *f, 
             out[(size_t)i * ld + j] = STORE((p + wgt * s) - lam * rho);              \
         }                                                                            \
     /* (3) max-norm of the input iterate's residual */                               \
-    if (norms) norm_pass_##SUF(temp, n, f, ld_f, c, NULL, 0, norms);                 \
+    if (norms) norm_pass_##SUF(temp, n, f, ld_f, c, NULL, 0, NULL, norms);           \
     write_out_ghosts_##SUF(in, out, n, ld, bcs);                                     \
 }                                                                                    \
 void ox_sweep_sides_##SUF(const ST *in, ST *out, int n, int ld, const ST *f,         \

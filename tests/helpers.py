@@ -103,26 +103,74 @@ def gpu_relax(phi0: np.ndarray, f: np.ndarray, n: int, h: float, lam: float, nsw
 
 
 def oracle_relax(phi0: np.ndarray, f: np.ndarray, n: int, h: float, lam: float, nsweeps: int,
-                 dt: str, bc: int = 0, resmode: int = oracle.RES_FINAL):
-    out, mx, sq = oracle.relax(oracle_input(phi0, dt), oracle_input(f, dt), n, h, lam, nsweeps,
-                               bc=bc, resmode=resmode)
-    return out, mx, sq
+                 dt: str, bc: int = 0, resmode: int = oracle.RES_FINAL, exact_sum: bool = True):
+    """The oracle's nsweeps sweeps; returns (phi_out, max|r|, sum r^2).  With exact_sum
+    the sum of squares returned is the exact sum (math.fsum) of the oracle's own FP64
+    squares of the measured iterate (phi_out for FINAL, the iterate before the last sweep
+    for LAGGED), after checking that the oracle's max is the max of those residuals and
+    that its sequential row-major sum lies within its own bound of the exact one."""
+    pin, fin = oracle_input(phi0, dt), oracle_input(f, dt)
+    out, mx, sq = oracle.relax(pin, fin, n, h, lam, nsweeps, bc=bc, resmode=resmode)
+    if not exact_sum or resmode == oracle.RES_NONE or (nsweeps == 0 and resmode == oracle.RES_LAGGED):
+        return out, mx, sq
+    if resmode == oracle.RES_FINAL:
+        measured = out
+    else:  # the norm of the last sweep's input: the iterate after nsweeps - 1 sweeps
+        measured, _, _ = oracle.relax(pin, fin, n, h, lam, nsweeps - 1, bc=bc, resmode=oracle.RES_NONE)
+    rd, mx2, sq2 = oracle.residual_terms(np.ascontiguousarray(measured), fin, n, h, bc=bc)
+    if np.isnan(mx):
+        assert np.isnan(mx2)
+        return out, mx, sq
+    assert mx2 == mx and sq2 == sq, (mx, mx2, sq, sq2)
+    ex = oracle.exact_sum_squares(rd)
+    # the oracle's own sum: n^2 - 1 additions in a row (recursive summation bound)
+    assert abs(sq - ex) <= gamma(n * n) * ex + 1e-300, (sq, ex)
+    return out, mx, ex
 
 
-def sum_tolerance(terms: int) -> float:
-    """Relative tolerance for two FP64 sums of the same `terms` non-negative numbers in
-    different orders: the oracle adds them one after another, whose error bound is
-    (terms - 1) * 2^-53 of the sum; the GPU's tree order is far tighter.  Floor 1e-12."""
-    return max(1e-12, terms * 2.0 ** -53)
+def oracle_residual_exact(phi: np.ndarray, f: np.ndarray, n: int, h: float, dt: str, bc: int = 0):
+    """The oracle's residual of phi (storage of dt): (r in storage, max|r|, exact sum of
+    the FP64 squares), the sum checked against the oracle's own sequential one."""
+    pin, fin = oracle_input(phi, dt), oracle_input(f, dt)
+    r, mx, sq = oracle.residual(pin, fin, n, h, bc=bc)
+    rd, mx2, sq2 = oracle.residual_terms(pin, fin, n, h, bc=bc)
+    assert (mx2, sq2) == (mx, sq) or np.isnan(mx)
+    ex = oracle.exact_sum_squares(rd)
+    assert np.isnan(mx) or abs(sq - ex) <= gamma(n * n) * ex + 1e-300, (sq, ex)
+    return r, mx, ex
 
 
-def assert_norms(gpu_norms, mx, sq, n=None, rel_sum=None):
+def gamma(depth: int) -> float:
+    """gamma_d = d u / (1 - d u), u = 2^-53: a sum whose every term passes through at
+    most d rounded additions differs from the exact sum by at most gamma_d times the sum
+    of the magnitudes (Higham, Accuracy and Stability of Numerical Algorithms, Sec. 4.2)."""
+    u = 2.0 ** -53
+    return depth * u / (1.0 - depth * u)
+
+
+def gpu_sum_depth(n: int, rows: int = 300) -> int:
+    """Most additions any square passes through in the GPU's sum: a lane adds the cells
+    of its band one after another (rows x 4 values at most), a wave combines its 64
+    lanes in a 6-level tree, the partial of each wave (or 64-lane row segment, for the
+    unfused kernels, plus 3 for their 4-wave blocks) is added sequentially by one of
+    1024 threads, and those in a 10-level tree.  `rows`: the tallest band a launch of the
+    test uses (300 is the tallest any test forces)."""
+    per_lane = min(n + 2, rows) * 4
+    partials = (n + 2) * ((n + 2 + 63) // 64)  # more than any launch writes
+    return per_lane + 6 + 3 + (partials + 1023) // 1024 + 10
+
+
+def assert_norms(gpu_norms, mx, sq, n=None, rel_sum=None, rows: int = 300):
+    """max|r| bit for bit; the sum of squares within gamma_D of `sq`, where D is the
+    GPU's summation depth (gpu_sum_depth) -- with `sq` the exact sum from oracle_relax
+    that bounds the GPU's rounding alone, well under 1e-12 relative at every size tested."""
     gmx, gsq = float(gpu_norms[0]), float(gpu_norms[1])
     if np.isnan(mx):
         assert np.isnan(gmx)
         return
     assert gmx == mx, (gmx, mx)  # the max is exact
-    tol = rel_sum if rel_sum is not None else (sum_tolerance(n * n) if n else 1e-12)
+    tol = rel_sum if rel_sum is not None else (gamma(gpu_sum_depth(n, rows)) if n else 1e-12)
+    assert tol <= 1e-12 or rel_sum is not None, tol
     assert abs(gsq - sq) <= tol * abs(sq) + 1e-300, (gsq, sq, tol)
 
 

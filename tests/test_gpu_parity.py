@@ -1,8 +1,9 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
 Bar: bit-exact for every element of phi (interior and edge ghosts) in FP64,
-FP32 and BF16, and for max|r|; sum r^2 within 1e-12 relative (it is summed in
-a different order on the two sides)."""
+FP32 and BF16, and for max|r|; sum r^2 within gamma_D of the exact sum of the
+oracle's own squares, D the GPU's summation depth (under 2e-13 relative at
+these sizes; the two sides add the same squares in different orders)."""
 import numpy as np
 import pytest
 import torch
@@ -235,7 +236,7 @@ def test_residual_matches_oracle(ctx, dt, bc):
     norms = torch.zeros(2, dtype=torch.float64, device="cuda")
     px.residual(pd, n, fd, h, norms, ctx, bc=bc, r=r)
     torch.cuda.synchronize()
-    rr, mx, sq = oracle.residual(H.oracle_input(phi, dt), H.oracle_input(f, dt), n, h, bc=bc)
+    rr, mx, sq = H.oracle_residual_exact(phi, f, n, h, dt, bc=bc)
     assert np.array_equal(H.bits(H.to_storage_np(r, dt)), H.bits(rr))
     H.assert_norms(norms.cpu().numpy(), mx, sq, n=n)
 
@@ -270,9 +271,12 @@ def test_unfused_sweep_equals_fused(ctx, dt):
 @pytest.mark.parametrize("k", [2, 5, 8])
 def test_interior_unrolled_path_matches_oracle(dt, k):
     """Interior tiles of launches without norms with k + 1 a multiple of 3 run the
-    unrolled-ring loop; on a grid with interior tiles in every direction, several launches
-    (the last one with final norms) at band heights that do and do not fill whole unrolled
-    blocks give the oracle's result bit for bit."""
+    unrolled-ring loop; several launches (the last one with final norms) at band heights
+    that do and do not fill whole unrolled blocks give the oracle's result bit for bit.
+    At n = 333 the 128-column FP64 waves get interior tiles in every direction; the
+    256-column FP32 and BF16 waves get none below n of about 490 (their edge tiles are
+    what this case checks), so their interior tiles are covered at n >= 520 in
+    test_gpu_interior.py."""
     H.require_gpu()
     n = 333
     h = 1.0 / n

@@ -475,3 +475,40 @@ def test_periodic_stencil_of_mode_is_its_eigenvalue():
     # the mode's samples carry the rounding of cos at arguments up to ~40: a few 1e-15
     # each, times the stencil's weights (sum 8)
     np.testing.assert_allclose(s, ev * mode, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_residual_terms_are_the_norms_terms(dt):
+    """The per-cell residuals behind the exact sum of squares are the numbers the norm
+    pass takes: their max magnitude is the oracle's max|r| bit for bit, they equal the
+    stored residual in FP64 and FP32 (and round to it in BF16), and their squares summed
+    exactly (math.fsum) lie within the recursive-summation bound of the oracle's own
+    row-major sum; the exact sum keeps what a sequential sum loses past 2^53."""
+    n = 45
+    h, _ = lam_of(n)
+    phi = W.uniform_phi(n, 25)
+    f = W.uniform_rhs(n, 26)
+    if dt == "f64":
+        p, q = phi, f
+    elif dt == "f32":
+        p, q = phi.astype(np.float32), f.astype(np.float32)
+    else:
+        p, q = oracle.f32_to_bf16_bits(phi.astype(np.float32)), oracle.f32_to_bf16_bits(f.astype(np.float32))
+    r, mx, sq = oracle.residual(p, q, n, h)
+    rd, mx2, sq2 = oracle.residual_terms(p, q, n, h)
+    assert (mx2, sq2) == (mx, sq)
+    assert np.abs(rd).max() == mx
+    if dt == "bf16":
+        assert np.array_equal(oracle.f32_to_bf16_bits(rd.astype(np.float32)), r)
+    else:
+        assert np.array_equal(rd.view(np.int64), r.astype(np.float64).view(np.int64))
+    ex = oracle.exact_sum_squares(rd)
+    u = 2.0 ** -53
+    assert abs(sq - ex) <= (n * n) * u * ex
+    # squares 2^54 and four 1s: a sequential double sum stays at 2^54 (ulp 4), the exact
+    # sum 2^54 + 4 is representable
+    terms = np.array([2.0 ** 27, 1.0, 1.0, 1.0, 1.0])
+    seq = 0.0
+    for t in terms:
+        seq += t * t
+    assert seq == 2.0 ** 54 and oracle.exact_sum_squares(terms) == 2.0 ** 54 + 4.0
