@@ -159,7 +159,10 @@ int px_jacobi_update(void *phi, int n, int ld, int dtype, const void *s, int ld_
                      const void *f, int ld_f, double h, double lambda, void *stream);
 
 /*
- * Fused relaxation: nsweeps damped-Jacobi sweeps phi_in -> phi_out, each
+ * Fused relaxation (Section IV: the Jacobi step of Eq. 3 with the stencil of
+ * Eq. 1, fused with the max-norm as in the generated CPU loop of Fig. 5 and
+ * the GPU kernel of Fig. 7, which compute the update and the norm in one pass
+ * over the grid): nsweeps damped-Jacobi sweeps phi_in -> phi_out, each
  * sweep computing the stencil, the update and (on the sweep resmode asks
  * for) the residual norms in one pass over memory.  Several sweeps run per
  * kernel launch (temporal blocking): tblock in 1..8 sweeps per launch, 0 =
