@@ -178,6 +178,26 @@ int px_relax_fused(const void *phi_in, void *phi_out, int n, int ld, int dtype, 
                    int ld_f, double h, double lambda, int nsweeps, int tblock, int bc,
                    int resmode, double *norms, px_ctx *ctx, void *stream);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one launch of
+ * px_relax_fused -- 1 <= nsweeps <= 8 sweeps, temporally blocked in a single
+ * kernel launch, default tile height -- with no context.  Same arguments,
+ * results and errors as px_relax_fused otherwise (bit-identical outputs and
+ * norms).  Longer runs alternate phi_in/phi_out buffers of the caller's own.
+ * The reduction partials live in a fixed device array of the library
+ * (PX_NOALLOC_MAX_PARTIALS slots of 16 bytes = 2 MiB on every GPU the call
+ * runs on, held until the process ends); grids needing more partials than it
+ * holds are rejected with PX_EINVAL (every grid up to n = 16384 fits).  Runs on
+ * the current HIP device.  Calls that overlap on one GPU race on that array:
+ * serialise them (one stream, or events).  Allocates nothing: the first call
+ * on a device only looks the array's address up.
+ */
+#define PX_NOALLOC_MAX_PARTIALS (1 << 17)
+int px_relax_fused_noalloc(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f,
+                           int ld_f, double h, double lambda, int nsweeps, int bc, int resmode,
+                           double *norms, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Iterative solve (the paper's Algorithm iterated to a tolerance).         */
 /* ---------------------------------------------------------------------- */

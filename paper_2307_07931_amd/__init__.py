@@ -77,7 +77,7 @@ EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile
            "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched",
            "px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
            "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
-           "px_net_make_pair", "px_correction_step", "px_solve_learned")
+           "px_net_make_pair", "px_correction_step", "px_solve_learned", "px_relax_fused_noalloc")
 
 _lib = None
 
@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
     L.px_residual.argtypes = [P, I, I, I, P, I, D, I, P, I, P, P, P]
     L.px_jacobi_update.argtypes = [P, I, I, I, P, I, P, I, D, D, P]
     L.px_relax_fused.argtypes = [P, P, I, I, I, P, I, D, D, I, I, I, I, P, P, P]
+    L.px_relax_fused_noalloc.argtypes = [P, P, I, I, I, P, I, D, D, I, I, I, P, P]
     L.px_solve.argtypes = [P, I, I, I, P, I, D, D, ctypes.POINTER(_SolveOpts),
                            ctypes.POINTER(_SolveStats), P, P]
     L.px_autotune.argtypes = [P, P, I, I, I, P, I, I, P, P, ctypes.POINTER(I), ctypes.POINTER(I),
@@ -277,6 +278,20 @@ def relax_fused(phi_in, phi_out, n, f, h, lam, nsweeps, ctx: Context, tblock=0,
     _check(lib().px_relax_fused(_ptr(phi_in), _ptr(phi_out), n, ld, dtype_code(phi_in), _ptr(f), ldf,
                                 float(h), float(lam), int(nsweeps), int(tblock), int(bc), int(resmode),
                                 _ptr(norms), ctx.handle, _stream_handle(stream)))
+    return phi_out
+
+
+def relax_fused_noalloc(phi_in, phi_out, n, f, h, lam, nsweeps, bc=BC_DIRICHLET0, resmode=RES_FINAL,
+                       norms=None, stream=None):
+    """One launch of 1..8 fused sweeps phi_in -> phi_out with no context: the library
+    allocates nothing (its reduction partials sit in a fixed device array)."""
+    ld = _ld(phi_in, n + 2, n + 2, "phi_in")
+    if _ld(phi_out, n + 2, n + 2, "phi_out") != ld:
+        raise ValueError("phi_in and phi_out must share ld")
+    ldf = _ld(f, n, n, "f")
+    _check(lib().px_relax_fused_noalloc(_ptr(phi_in), _ptr(phi_out), n, ld, dtype_code(phi_in), _ptr(f), ldf,
+                                        float(h), float(lam), int(nsweeps), int(bc), int(resmode), _ptr(norms),
+                                        _stream_handle(stream)))
     return phi_out
 
 

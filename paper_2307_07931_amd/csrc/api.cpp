@@ -12,6 +12,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -417,6 +418,94 @@ int px_relax_fused(const void *phi_in, void *phi_out, int n, int ld, int dtype, 
     }
     return run_sweeps(ctx, dtype, phi_in, phi_out, tmp, n, ld, f, ld_f, h, lambda, nsweeps, k, bc,
                       resmode, norms, s);
+}
+
+}  // extern "C"
+
+// ---- relaxation without allocation ---------------------------------------------------
+// Reduction partials of px_relax_fused_noalloc: a fixed device array, one copy per GPU the
+// library runs on, held until the process ends.  Slots [0, NOALLOC_PARTIALS) hold the
+// max|r| bit patterns, [NOALLOC_PARTIALS, 2 NOALLOC_PARTIALS) the sums of squares.  Every
+// tile of a launch writes its own slot before the reduction reads it, so nothing needs
+// clearing between calls.  The array's name is only a host-side handle: kernels get the
+// address hipGetSymbolAddress returns for the current device.
+constexpr int NOALLOC_PARTIALS = PX_NOALLOC_MAX_PARTIALS;
+static __device__ __align__(256) unsigned long long scratch[2 * NOALLOC_PARTIALS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[NOALLOC_MAX_DEVICES];
+
+// The device address of `scratch` on the current device (looked up once per device).
+int noalloc_scratch(void **out)
+{
+    int dev = -1;
+    PX_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(PX_EUNSUPPORTED, "device %d beyond the %d this build supports", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        PX_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p) return fail(PX_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return PX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int px_relax_fused_noalloc(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f,
+                           int ld_f, double h, double lambda, int nsweeps, int bc, int resmode, double *norms,
+                           void *stream)
+{
+    int st = check_n_ld(n, ld, dtype);
+    if (st) return st;
+    if ((st = check_ptr(phi_in, dtype, "phi_in")) || (st = check_ptr(phi_out, dtype, "phi_out")))
+        return st;
+    if ((st = check_flat(f, n, ld_f, dtype, "f"))) return st;
+    if ((st = check_pos(h, "h")) || (st = check_pos(lambda, "lambda"))) return st;
+    if (nsweeps < 1 || nsweeps > 8)
+        return fail(PX_EINVAL, "nsweeps = %d outside [1, 8] (one launch; no ping-pong buffer)", nsweeps);
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (resmode < RES_NONE || resmode > RES_FINAL) return fail(PX_EINVAL, "unknown resmode %d", resmode);
+    if (resmode != RES_NONE && !norms) return fail(PX_EINVAL, "norms is NULL");
+    if (norms && reinterpret_cast<uintptr_t>(norms) % 8) return fail(PX_EINVAL, "norms is not 8-byte aligned");
+    const size_t gb = grid_bytes(n, ld, dtype);
+    if (overlap(phi_in, gb, phi_out, gb)) return fail(PX_EALIAS, "phi_out overlaps phi_in");
+    if (overlap(f, flat_bytes(n, ld_f, dtype), phi_out, gb)) return fail(PX_EALIAS, "phi_out overlaps f");
+    const int rows = relax_default_rows(dtype, n, nsweeps);
+    const int parts = relax_num_waves(dtype, n, nsweeps, resmode, rows);
+    if (resmode != RES_NONE && parts > NOALLOC_PARTIALS)
+        return fail(PX_EINVAL, "grid of n = %d needs %d reduction partials; the fixed scratch holds %d", n, parts,
+                    NOALLOC_PARTIALS);
+    void *base = nullptr;
+    if ((st = noalloc_scratch(&base))) return st;
+    RelaxLaunch a;
+    a.in = phi_in;
+    a.out = phi_out;
+    a.f = f;
+    a.n = n;
+    a.ld = ld;
+    a.ld_f = ld_f;
+    a.c = 1.0 / (h * h);
+    a.w = lambda / (h * h);
+    a.lam = lambda;
+    a.bc = bc;
+    a.sweeps = nsweeps;
+    a.resmode = resmode;
+    a.rows = rows;
+    a.part = Partials{static_cast<unsigned long long *>(base),
+                      reinterpret_cast<double *>(static_cast<unsigned long long *>(base) + NOALLOC_PARTIALS)};
+    hipStream_t s = (hipStream_t)stream;
+    PX_HIP(relax_launch(dtype, a, s), "relax kernel launch");
+    if (resmode != RES_NONE) PX_HIP(reduce_partials(a.part, parts, norms, s), "norm reduction launch");
+    return PX_OK;
 }
 
 int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f, int ld_f,

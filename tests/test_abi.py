@@ -82,6 +82,70 @@ def test_relax_validation(ctx, kw, code):
     assert px.last_error() != ""
 
 
+def relax_noalloc(**kw):
+    a = dict(phi_in=FAKE, phi_out=FAKE2, n=64, ld=66, dtype=px.F64, f=FAKE2 * 2, ld_f=64,
+             h=1 / 64, lam=1e-5, nsweeps=8, bc=0, resmode=2, norms=FAKE2 * 3)
+    a.update(kw)
+    P = ctypes.c_void_p
+    return px.lib().px_relax_fused_noalloc(P(a["phi_in"]), P(a["phi_out"]), a["n"], a["ld"], a["dtype"],
+                                           P(a["f"]), a["ld_f"], a["h"], a["lam"], a["nsweeps"], a["bc"],
+                                           a["resmode"], P(a["norms"]), None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n=0), px.EINVAL),
+    (dict(ld=65), px.EINVAL),
+    (dict(phi_in=0), px.EINVAL),
+    (dict(f=0), px.EINVAL),
+    (dict(dtype=7), px.EINVAL),
+    (dict(bc=5), px.EINVAL),
+    (dict(resmode=3), px.EINVAL),
+    (dict(norms=0), px.EINVAL),
+    (dict(h=0.0), px.EINVAL),
+    (dict(lam=float("nan")), px.EINVAL),
+    (dict(nsweeps=0), px.EINVAL),   # one launch of 1..8 sweeps only
+    (dict(nsweeps=9), px.EINVAL),
+    (dict(phi_out=FAKE + 8 * 100), px.EALIAS),
+    (dict(f=FAKE2 + 8 * 66), px.EALIAS),
+    # more reduction partials than the fixed array holds (rejected before any HIP call)
+    (dict(n=40000, ld=40002, phi_out=1 << 40, f=2 << 40, ld_f=40000, norms=3 << 40), px.EINVAL),
+])
+def test_relax_noalloc_validation(kw, code):
+    assert relax_noalloc(**kw) == code
+    assert px.last_error() != ""
+
+
+def test_relax_noalloc_fits_every_grid_up_to_16384():
+    """The fixed partials array holds the wave tiles of every default launch up to n = 16384
+    (the limit the header states), for every precision, sweep count and residual mode."""
+    from paper_2307_07931_amd import build  # noqa: F401  (the library is built)
+    cap = 1 << 17
+    for dtype, V in ((px.F64, 2), (px.F32, 4), (px.BF16, 4)):
+        for k in range(1, 9):
+            for rm in (1, 2):
+                nl = k + (1 if rm == 2 else 0)
+                rows = default_rows(dtype, 16384, k)
+                halo = 0 if nl == 1 else (nl + V - 1) // V * V
+                stride = 64 * V - 2 * halo
+                tiles = -(-(16384 + 2) // stride) * -(-(16384 + 2) // rows)
+                assert tiles <= cap, (dtype, k, rm, tiles)
+
+
+def default_rows(dtype, n, sweeps):
+    """The library's default tile height (relax_default_rows), restated."""
+    if dtype == px.F64:
+        rows = 48 if sweeps <= 2 else (38 if sweeps <= 6 else 32)
+    else:
+        rows = 20 if sweeps <= 7 else 32
+    rows = min(rows, max(8, (n + 2) // 16))
+    if (sweeps + 1) % 3 == 0:
+        u = sweeps + 1
+        rows -= (rows + 2 * sweeps) % u
+        if rows < 8:
+            rows += u
+    return rows
+
+
 def test_relax_bf16_alignment_is_two_bytes(ctx):
     # 2-byte alignment is enough for BF16; odd address is not
     assert relax(ctx, dtype=px.BF16, phi_in=FAKE + 1) == px.EINVAL
