@@ -386,6 +386,9 @@ typedef struct px_learned_stats {
     int64_t corrections;  /* correction steps kept                                     */
     int64_t rejected;     /* correction steps undone by the judge                      */
     int fell_back;        /* 1 when a non-finite step switched corrections off         */
+    int64_t discarded_sweeps; /* smoothing sweeps of undone steps: run, then discarded
+                                 with the step; included in base.sweeps and counted
+                                 against max_sweeps                                  */
 } px_learned_stats;
 
 /*

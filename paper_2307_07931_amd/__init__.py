@@ -63,7 +63,7 @@ class _LearnedOpts(ctypes.Structure):
 
 class _LearnedStats(ctypes.Structure):
     _fields_ = [("base", _SolveStats), ("corrections", ctypes.c_int64), ("rejected", ctypes.c_int64),
-                ("fell_back", ctypes.c_int)]
+                ("fell_back", ctypes.c_int), ("discarded_sweeps", ctypes.c_int64)]
 
 
 class _Problem(ctypes.Structure):
@@ -510,6 +510,7 @@ class LearnedStats(SolveStats):
     corrections: int = 0
     rejected: int = 0
     fell_back: int = 0
+    discarded_sweeps: int = 0  # sweeps of undone steps (included in sweeps)
 
 
 def solve_learned(phi, n, f, h, lam, ctx: Context, net: "Net | None" = None, use_net=1, rtol=1e-10,
@@ -530,4 +531,4 @@ def solve_learned(phi, n, f, h, lam, ctx: Context, net: "Net | None" = None, use
         _check(st)
     b = s.base
     return LearnedStats(st, b.sweeps, b.outer_steps, b.res_max, b.res_l2, b.rel_res_max, b.rel_res_l2,
-                        b.seconds, s.corrections, s.rejected, s.fell_back)
+                        b.seconds, s.corrections, s.rejected, s.fell_back, s.discarded_sweeps)

@@ -1126,6 +1126,10 @@ int px_solve_learned(void *phi, int n, int ld, const double *f, int ld_f, double
                 // residual: undo it
                 PX_HIP(copy_grid_launch(F64, save, cur, n, ld, s), "copy kernel launch");
                 S.rejected += 1;
+                // the undone step's smoothing sweeps were run all the same: they count
+                // against the budget and in the sweep total
+                S.base.sweeps += todo;
+                S.discarded_sweeps += todo;
                 r_fresh = false;
                 if (!finite) {
                     S.fell_back = 1;

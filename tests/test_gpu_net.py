@@ -243,9 +243,10 @@ def test_corrupted_network_falls_back_to_plain(ctx):
     phi, fd, h, lam = setup_problem(n, f)
     st = px.solve_learned(phi, n, fd, h, lam, ctx, net=net, rtol=1e-5, smooth_sweeps=smooth, tblock=8)
     assert st.rejected == 1 and st.fell_back == 1 and st.corrections == 0
+    assert st.discarded_sweeps == smooth  # the undone step's sweeps count as work done
     phi2, fd2, _, _ = setup_problem(n, f)
     st2 = px.solve(phi2, n, fd2, h, lam, ctx, mode=px.SOLVE_PLAIN, rtol=1e-5, check_every=smooth, tblock=8)
-    assert st.sweeps == st2.sweeps
+    assert st.sweeps - st.discarded_sweeps == st2.sweeps
     H.assert_grid_bitwise(phi.cpu().numpy(), phi2.cpu().numpy(), n)
     net.close()
 
@@ -261,13 +262,20 @@ def test_judge_undoes_steps_that_raise_the_residual(ctx):
     print(f"\njudge: {st.corrections} kept, {st.rejected} undone, {st.sweeps} sweeps")
     assert st.status == px.OK and st.rel_res_max <= 1e-6
     assert st.rejected >= 1 and st.fell_back == 0 and st.corrections >= 1
-    assert st.sweeps == st.outer_steps  # one sweep per kept or plain step; undone steps not counted
+    # one sweep per kept or plain step, and one per undone step (run, then discarded)
+    assert st.discarded_sweeps == st.rejected
+    assert st.sweeps == st.outer_steps + st.discarded_sweeps
 
 
 def test_training_reduces_loss_and_trained_net_converges(ctx):
     """Pairs from plain solves of the homogeneous problem, a short training run, and the
-    learned loop with the trained network reaching the tolerance; the gain over the
-    same loop without the network and over plain relaxation is printed."""
+    learned loop with the trained network reaching the tolerance, and what the network
+    gains.  Training and solves are deterministic, so the sweep counts are fixed on this
+    hardware (measured: 1968 sweeps with both directions, 9312 with the network's
+    direction alone, 5872 without the network, 27728 plain).  Bounds: with both
+    directions the trained network at least halves the sweeps of the loop without it; its
+    direction alone is the worse choice (more sweeps than without the network, which is
+    recorded, not hidden); the loop without the network beats plain relaxation."""
     n = 64
     fields = [W.error_field(n, W.SEED_TRAIN_BASE + s) for s in range(4)]
     X, T = learned.training_pairs(fields, ctx, snapshots=(16, 64, 256, 1024))
@@ -288,8 +296,12 @@ def test_training_reduces_loss_and_trained_net_converges(ctx):
     phi, fd, h, lam = setup_problem(n, f)
     plain = px.solve(phi, n, fd, h, lam, ctx, mode=px.SOLVE_PLAIN, rtol=1e-10, norm=1, check_every=16, tblock=8)
     print(f"\nlearned loop at n={n}: sweeps with the network direction {res['net'].sweeps}, with both "
-          f"directions {res['both'].sweeps}, without the network {res['nonet'].sweeps}, plain {plain.sweeps}")
+          f"directions {res['both'].sweeps}, without the network {res['nonet'].sweeps}, plain {plain.sweeps}; "
+          f"seconds {res['net'].seconds:.4f} / {res['both'].seconds:.4f} / {res['nonet'].seconds:.4f} / "
+          f"{plain.seconds:.4f}")
     assert res["nonet"].sweeps < plain.sweeps
+    assert res["both"].sweeps <= 0.5 * res["nonet"].sweeps, (res["both"].sweeps, res["nonet"].sweeps)
+    assert res["net"].sweeps > res["nonet"].sweeps  # the network's direction alone loses here
     net.close()
 
 

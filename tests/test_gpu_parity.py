@@ -337,3 +337,43 @@ def test_extreme_magnitudes_bitwise(dt, scale, resmode, k):
     assert np.isfinite(interior).all() and interior.max() > 0.01 * scale
     if resmode != px.RES_NONE:
         H.assert_norms(nm, mx, sq, n=n)
+
+
+# ------------------------------------------------------- band geometry --
+
+def band_count(n, rows):
+    return (n + 2 + rows - 1) // rows
+
+
+# (n, rows): an odd band count (the last band streams down alone), an even one, 4-row bands
+# (every band's pipeline drains before it has filled), a band meeting the next at the
+# ghost row (n + 1 = 9 rows * 10: the last band holds only row n + 1), a one-band grid
+GEOMETRY_GRIDS = [(100, 8), (100, 17), (61, 4), (89, 10), (30, 64), (777, 29)]
+
+
+@pytest.mark.parametrize("k", [2, 5, 8])
+@pytest.mark.parametrize("dt", ["f64", "f32", "bf16"])
+def test_band_geometry_edge_cases_match_oracle(dt, k):
+    """The unrolled-ring loop (launches without norms, k + 1 a multiple of 3) on band
+    layouts at the edges of its geometry, three launches (and, with a residual mode, a
+    fourth on the generic loop), every boundary rule: bit for bit equal to the oracle."""
+    H.require_gpu()
+    assert band_count(100, 8) % 2 == 1 and band_count(100, 17) % 2 == 0
+    assert (89 + 1) % 10 == 0 and band_count(30, 64) == 1
+    for i, (n, rows) in enumerate(GEOMETRY_GRIDS):
+        h, lam = params(n)
+        bc = (0, 1, 2)[(i + k) % 3]
+        rm = px.RES_NONE if i % 2 == 0 else px.RES_FINAL
+        N = 3 * k + (0 if rm == px.RES_NONE else 1)
+        phi0 = W.uniform_phi(n, 7300 + 10 * i + k)
+        f = W.uniform_rhs(n, 7400 + 10 * i + k)
+        c = px.Context()
+        c.set_tile_rows(rows)
+        print(f"case: geometry {dt} n={n} rows={rows} k={k} bc={bc} res={rm} sweeps={N}", flush=True)
+        got, nm = H.gpu_relax(phi0, f, n, h, lam, N, dt, c, tblock=k, bc=bc, resmode=rm)
+        c.close()
+        ref, mx, sq = H.oracle_relax(phi0, f, n, h, lam, N, dt, bc=bc, resmode=rm)
+        mask = np.ones((n + 2, n + 2), dtype=bool) if bc == px.BC_PERIODIC else None
+        H.assert_grid_bitwise(got, ref, n, mask=mask, what=f"geometry {dt} n={n} rows={rows} k={k} bc={bc}")
+        if rm != px.RES_NONE:
+            H.assert_norms(nm, mx, sq, n=n, rows=rows)
