@@ -21,6 +21,7 @@ using namespace px;
 
 struct px_tuned {
     int n = 0, ld = 0, k = 0, rows = 0;
+    int rows_norm = 0;  // tile rows for the launches of k sweeps that also take the norms
     double gcells = 0.0;
 };
 
@@ -182,13 +183,14 @@ int default_tblock(const px_ctx *ctx, int dtype, int n, int ld)
     return 8;
 }
 
-// Tile height for a launch of `ks` sweeps: explicit override, then the tuned value
-// (when the tuned k is the one launched), then the built-in default.
-int pick_rows(const px_ctx *ctx, int dtype, int n, int ld, int ks)
+// Tile height for a launch of `ks` sweeps (residual mode rm): explicit override, then the
+// tuned value (when the tuned k is the one launched; launches with norms have their own),
+// then the built-in default.
+int pick_rows(const px_ctx *ctx, int dtype, int n, int ld, int ks, int rm = RES_NONE)
 {
     if (ctx->tile_rows > 0) return ctx->tile_rows;
     if (const px_tuned *t = tuned_for(ctx, dtype, n, ld))
-        if (t->k == ks) return t->rows;
+        if (t->k == ks) return (rm != RES_NONE && t->rows_norm > 0) ? t->rows_norm : t->rows;
     return relax_default_rows(dtype, n, ks);
 }
 
@@ -221,7 +223,7 @@ int run_sweeps(px_ctx *ctx, int dtype, const void *src, void *dst, void *tmp, in
         a.bc = bc;
         a.sweeps = ks;
         a.resmode = (i == L - 1) ? resmode : RES_NONE;
-        a.rows = forced_rows > 0 ? forced_rows : pick_rows(ctx, dtype, n, ld, ks);
+        a.rows = forced_rows > 0 ? forced_rows : pick_rows(ctx, dtype, n, ld, ks, a.resmode);
         a.part = partials(ctx);
         if (a.resmode != RES_NONE) {
             int st = ensure_partials(ctx, (size_t)relax_num_waves(dtype, n, ks, a.resmode, a.rows));
@@ -319,7 +321,7 @@ int px_ctx_reserve(px_ctx *ctx, int n, int ld, int dtype)
     size_t parts = (size_t)pointwise_num_blocks(n);
     for (int k = 1; k <= 8; ++k)
         for (int rm = RES_LAGGED; rm <= RES_FINAL; ++rm) {
-            parts = std::max(parts, (size_t)relax_num_waves(dtype, n, k, rm, pick_rows(ctx, dtype, n, ld, k)));
+            parts = std::max(parts, (size_t)relax_num_waves(dtype, n, k, rm, pick_rows(ctx, dtype, n, ld, k, rm)));
         }
     if ((st = ensure_partials(ctx, parts))) return st;
     return ensure_norms(ctx);
@@ -575,14 +577,20 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
             }
         }
     }
-    constexpr int RUN = 8, ROUNDS = 3;
+    // Second pass: runs of RUN launches as a sweep loop makes them -- each launch reading
+    // the previous one's output, alternating between phi_out and the context's grid -- so
+    // that what the caches hold between launches is what a real run sees (single launches
+    // re-read the same input, which the Infinity Cache may still hold, and rank tile
+    // heights differently).
+    constexpr int RUN = 24, ROUNDS = 3;  // runs as long as a 200-sweep call at k = 8
+    if (!err) err = ensure_grid(ctx, gb);
     double g2[TOP] = {};
     for (int round = 0; round < ROUNDS && !err; ++round) {
         for (int i = 0; i < TOP && !err; ++i) {
             if (top[i].k == 0) continue;
             hipError_t he = hipEventRecord(e0, s);
-            for (int l = 0; l < RUN && !err && he == hipSuccess; ++l)
-                err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, top[i].k,
+            if (he == hipSuccess)
+                err = run_sweeps(ctx, dtype, phi_in, phi_out, ctx->grid, n, ld, f, ld_f, h, lambda, RUN * top[i].k,
                                  top[i].k, bc, RES_NONE, nullptr, s, top[i].rows);
             if (err) break;
             if (he == hipSuccess) he = hipEventRecord(e1, s);
@@ -597,15 +605,47 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
             g2[i] = std::max(g2[i], g);
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (err) return err;
     int bi = 0;
     for (int i = 1; i < TOP; ++i)
         if (g2[i] > g2[bi]) bi = i;
     const int bk = top[bi].k, br = top[bi].rows;
     const double bg = g2[bi];
+    // third pass: the tile height of the winner's launches that also take the norms (their
+    // pipeline holds one more level, the residual's, so they favour other heights): the
+    // fastest of three single launches per candidate
+    int brn = 0;
+    if (!err && bk > 0) err = ensure_norms(ctx);
+    float best_norm = 0.f;
+    for (int rows : ROWS) {
+        if (err || rows > std::max(8, n + 2)) break;
+        if ((err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, bk, bk, bc, RES_FINAL,
+                              ctx->norms_dev, s, rows)))
+            break;
+        for (int rep = 0; rep < 3 && !err; ++rep) {
+            hipError_t he = hipEventRecord(e0, s);
+            if (he == hipSuccess)
+                err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, bk, bk, bc,
+                                 RES_FINAL, ctx->norms_dev, s, rows);
+            if (err) break;
+            if (he == hipSuccess) he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float one = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&one, e0, e1);
+            if (he != hipSuccess) {
+                err = hip_fail(he, "autotune timing");
+                break;
+            }
+            if (brn == 0 || one < best_norm) {
+                best_norm = one;
+                brn = rows;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err) return err;
     px_tuned &t = ctx->tuned[dtype];
+    t.rows_norm = brn;
     t.n = n;
     t.ld = ld;
     t.k = bk;
