@@ -55,10 +55,15 @@ TRAFFIC_SHA256 = "ccf5f4744f2a24bff878af30386f9903b997e9cca9883b07d9fa98a2d4eb81
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
     (8, 29): (179992.35, 131362.04), (8, 32): (199995.17, 131354.13), (8, 38): (171556.85, 131356.15),
-    (8, 40): (191047.50, 131357.48), (8, 44): (174396.93, 131352.61), (8, 47): (163440.73, 131352.11),
+    (8, 40): (191047.50, 131357.48), (8, 44): (174396.93, 131352.61), (8, 47): (163030.84, 131351.50),
     (8, 48): (184516.52, 131353.54),
-    (1, 20): (160338.08, 131271.72), (1, 47): (147411.16, 131271.52), (1, 64): (141696.22, 131268.44),
+    (1, 20): (160338.08, 131271.72), (1, 47): (147406.59, 131271.57), (1, 64): (141696.22, 131268.44),
 }
+# The same launches' memory-side request counters (TCC_EA0_RDREQ_DRAM_32B_sum and
+# TCC_EA0_WRREQ_WRITE_DRAM_32B_sum, 32-byte units, no scaling: the copy reads and writes
+# exactly its 1 GiB in them).  They count L2 misses sent to memory; no gfx950 counter
+# separates Infinity-Cache hits from HBM accesses.
+TRAFFIC_DRAM_32B = {(8, 47): (10348838, 4203216), (1, 47): (9432031, 4200688)}
 VARIANT_ROWS = (12, 16, 20, 29, 38, 47, 64, 96)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
@@ -72,7 +77,11 @@ def measured_traffic(k, rows):
     if hashlib.sha256(src).hexdigest() != TRAFFIC_SHA256 or (k, rows) not in TRAFFIC_KIB:
         return None
     fk, wk = TRAFFIC_KIB[(k, rows)]
-    return {"read": fk * 1024 * TRAFFIC_SCALE[0], "write": wk * 1024 * TRAFFIC_SCALE[1]}
+    out = {"read": fk * 1024 * TRAFFIC_SCALE[0], "write": wk * 1024 * TRAFFIC_SCALE[1]}
+    if (k, rows) in TRAFFIC_DRAM_32B:
+        dr, dw = TRAFFIC_DRAM_32B[(k, rows)]
+        out["memory_side"] = {"read": dr * 32, "write": dw * 32}
+    return out
 
 
 def log(*a):
@@ -804,6 +813,10 @@ def main():
         hbm_view["traffic_write"] = round(tr["write"])
         hbm_view["traffic_over_algorithmic"] = round((tr["read"] + tr["write"]) / hbm_view["alg_bytes_per_launch"], 3)
         hbm_view["actual_GBs"] = round((tr["read"] + tr["write"]) / per_launch_s / 1e9, 1)
+        if "memory_side" in tr:
+            ms_ = tr["memory_side"]
+            hbm_view["memory_side_read"] = ms_["read"]
+            hbm_view["memory_side_write"] = ms_["write"]
     # roofline: arithmetic intensity of a launch (k sweeps: 9k FLOP per 24 B of HBM traffic
     # per cell) against the ridge point of the no-FMA FP64 peak over the HBM peak; below
     # the ridge (every k <= 8: at most 3 FLOP/B against 4.9) the HBM roof binds
