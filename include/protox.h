@@ -354,6 +354,16 @@ int px_net_loss_grad(px_net *net, const float *x, const float *t, int batch, int
  * gradient of the last px_net_loss_grad call, then re-rounds the bfloat16 copies. */
 int px_net_adam(px_net *net, float lr, void *stream);
 
+/*
+ * The same y as px_net_forward, bit for bit, for inference: the first two layers run as
+ * one kernel that computes layer 1 on the fly into the second layer's input patches, so
+ * the 64-byte-per-pixel layer-1 activations never go through memory.  The hidden
+ * activations are not kept (px_net_activation then fails until the next
+ * px_net_forward).  The learned refinement loop evaluates the network this way.
+ */
+int px_net_infer(px_net *net, const void *x, int x_dtype, int ldx, int batch, int H, int W,
+                 double x_scale, float *y, int ldy, void *stream);
+
 /* Copy the hidden activation of layer 1, 2 or 3 of the last forward pass
  * (bfloat16 bit patterns, channels last: batch*H*W*32 values) to out (device). */
 int px_net_activation(px_net *net, int layer, uint16_t *out, void *stream);

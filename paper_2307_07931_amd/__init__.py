@@ -77,7 +77,8 @@ EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile
            "px_jacobi_update", "px_relax_fused", "px_solve", "px_relax_batched", "px_solve_batched",
            "px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
            "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
-           "px_net_make_pair", "px_correction_step", "px_solve_learned", "px_relax_fused_noalloc")
+           "px_net_make_pair", "px_correction_step", "px_solve_learned", "px_relax_fused_noalloc",
+           "px_net_infer")
 
 _lib = None
 
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
     L.px_net_set_weights.argtypes = [P, F]
     L.px_net_get_weights.argtypes = [P, F]
     L.px_net_forward.argtypes = [P, P, I, I, I, I, I, D, P, I, P]
+    L.px_net_infer.argtypes = [P, P, I, I, I, I, I, D, P, I, P]
     L.px_net_loss_grad.argtypes = [P, P, P, I, I, I, I, P, P, P]
     L.px_net_adam.argtypes = [P, ctypes.c_float, P]
     L.px_net_activation.argtypes = [P, I, P, P]
@@ -126,7 +128,7 @@ def lib() -> ctypes.CDLL:
     L.px_solve_learned.argtypes = [P, I, I, P, I, D, D, P, ctypes.POINTER(_LearnedOpts),
                                    ctypes.POINTER(_LearnedStats), P, P]
     for nm in ("px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
-               "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
+               "px_net_forward", "px_net_infer", "px_net_loss_grad", "px_net_adam", "px_net_activation",
                "px_net_make_pair", "px_correction_step", "px_solve_learned",
                "px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
                "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
@@ -430,9 +432,11 @@ class Net:
         _check(lib().px_net_get_weights(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return a
 
-    def forward(self, x, y, x_scale=1.0, stream=None):
+    def forward(self, x, y, x_scale=1.0, stream=None, infer=False):
         """y = N(x * x_scale); x: (B, H, ldx) or (H, ldx) float64/float32 with unit column
-        stride (the first W columns used, W = y's width); y: float32 of shape (B, H, >= W)."""
+        stride (the first W columns used, W = y's width); y: float32 of shape (B, H, >= W).
+        infer=True: the same y through px_net_infer (layers 1 and 2 fused, hidden
+        activations not kept)."""
         x3 = x if x.dim() == 3 else x.unsqueeze(0)
         y3 = y if y.dim() == 3 else y.unsqueeze(0)
         B, H, W = y3.shape[0], y3.shape[1], y3.shape[2]
@@ -443,8 +447,9 @@ class Net:
         ldx, ldy = x3.stride(1), y3.stride(1)
         if x3.stride(0) != H * ldx or y3.stride(0) != H * ldy:
             raise ValueError("images must be stored back to back (stride(0) == H * stride(1))")
-        _check(lib().px_net_forward(self._h, _ptr(x3), dtype_code(x3), ldx, B, H, W, float(x_scale),
-                                    _ptr(y3), ldy, _stream_handle(stream)))
+        fn = lib().px_net_infer if infer else lib().px_net_forward
+        _check(fn(self._h, _ptr(x3), dtype_code(x3), ldx, B, H, W, float(x_scale), _ptr(y3), ldy,
+                  _stream_handle(stream)))
         return y
 
     def loss_grad(self, x, t, loss=LOSS_MSE, loss_out=None, grad=None, stream=None):

@@ -88,8 +88,32 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
 constexpr int LT_ROWS = 4, LT_PX = 64;
 static_assert(LT_ROWS * LT_PX == BX, "one pixel per thread");
 
+// Layer 1 of one pixel from its 3 x 3 input neighbourhood xv (tap order, BF16 values held
+// as FP32): 32 channels, each an FP32 fused multiply-add chain over the 9 taps, ReLU,
+// rounded to BF16 and packed in pairs.  l1_fwd_kernel and the fused first convolution
+// both call it, so both produce the same bits.
+__device__ __forceinline__ void l1_pixel(const float (&xv)[9], const float *__restrict__ sw, unsigned (&pk)[C / 2])
+{
+#pragma unroll
+    for (int co = 0; co < C; co += 2) {
+        float acc0 = 0.0f, acc1 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            acc0 = __builtin_fmaf(sw[co * 9 + t], xv[t], acc0);
+            acc1 = __builtin_fmaf(sw[(co + 1) * 9 + t], xv[t], acc1);
+        }
+        pk[co / 2] = (unsigned)f32_to_bf16_rne(relu(acc0)) | ((unsigned)f32_to_bf16_rne(relu(acc1)) << 16);
+    }
+}
+
+// The first layer's input: x (FP64 or FP32) times `scale`, rounded to FP32, then to BF16.
+template <typename TX> __device__ __forceinline__ float l1_input(TX v, double scale)
+{
+    return bf16_to_f32(f32_to_bf16_rne((float)((double)v * scale)));
+}
+
 // Layer 1: x (rows of ldx, FP64 or FP32) times `scale`, rounded to FP32 and then to
-// BF16, -> 32 channels, ReLU.  FP32 accumulation (fused multiply-add allowed).
+// BF16, -> 32 channels, ReLU.  FP32 accumulation (fused multiply-add).
 template <typename TX>
 __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, int ldx, double scale,
                                                     const float *__restrict__ sw, bf16 *__restrict__ a1, int B,
@@ -105,8 +129,7 @@ __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, in
         const int pr = q / (LT_PX + 2), pc = q % (LT_PX + 2);
         const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
         float v = 0.0f;
-        if (ii >= 0 && ii < H && jj >= 0 && jj < W)
-            v = bf16_to_f32(f32_to_bf16_rne((float)((double)x[((long long)b * H + ii) * ldx + jj] * scale)));
+        if (ii >= 0 && ii < H && jj >= 0 && jj < W) v = l1_input(x[((long long)b * H + ii) * ldx + jj], scale);
         sx[q] = v;
     }
     __syncthreads();
@@ -117,16 +140,7 @@ __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, in
 #pragma unroll
     for (int t = 0; t < 9; ++t) xv[t] = sx[(r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))];
     unsigned pk[C / 2];
-#pragma unroll
-    for (int co = 0; co < C; co += 2) {
-        float acc0 = 0.0f, acc1 = 0.0f;
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            acc0 += sw[co * 9 + t] * xv[t];
-            acc1 += sw[(co + 1) * 9 + t] * xv[t];
-        }
-        pk[co / 2] = (unsigned)f32_to_bf16_rne(relu(acc0)) | ((unsigned)f32_to_bf16_rne(relu(acc1)) << 16);
-    }
+    l1_pixel(xv, sw, pk);
     uint4 *dst = reinterpret_cast<uint4 *>(a1 + (((long long)b * H + i) * W + j) * C);
 #pragma unroll
     for (int q = 0; q < 4; ++q) dst[q] = make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
@@ -173,6 +187,68 @@ __device__ __forceinline__ void patch_load(const bf16 *__restrict__ in, int tile
     }
 }
 
+// The matrix products and the epilogue of one tile, its patch and the weights in LDS.
+template <bool MIRROR>
+__device__ __forceinline__ void conv32_tile(const bf16 *__restrict__ sw, const bf16 *__restrict__ sp, int tile,
+                                            int tiles_w, int tiles_h, int H, int W, bf16 *__restrict__ out,
+                                            const bf16 *__restrict__ mask)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int n = lane & 31, kg = lane >> 5;
+    const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
+    const int i0 = th * TROWS, j0 = tw * TPX;
+    f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int pr = wv + 1 + tap_dy(t, MIRROR), pc = n + 1 + tap_dx(t, MIRROR);
+#pragma unroll
+        for (int c16 = 0; c16 < 2; ++c16) {
+            const int k0 = c16 * 16 + kg * 8;
+            bf16x8 av, b0, b1;
+            __builtin_memcpy(&av, sw + (t * C + n) * PSTR + k0, 16);
+            __builtin_memcpy(&b0, sp + (pr * PCOLS + pc) * PSTR + k0, 16);
+            __builtin_memcpy(&b1, sp + (pr * PCOLS + pc + 32) * PSTR + k0, 16);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+        }
+    }
+    const int i = i0 + wv;
+    if (i >= H) return;
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int j = j0 + half * 32 + n;
+        if (j >= W) continue;
+        const f32x16 &acc = half ? acc1 : acc0;
+        const long long p = ((long long)b * H + i) * W + j;
+        // lane holds output channels 8g + 4 kg + e (e = 0..3) of pixel j in acc[4g + e]
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int co = 8 * g + 4 * kg;
+            unsigned short v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float a = acc[4 * g + e];
+                if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
+                else a = relu(a);
+                v[e] = f32_to_bf16_rne(a);
+            }
+            uint2 pk;
+            pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
+            pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
+            *reinterpret_cast<uint2 *>(out + p * C + co) = pk;
+        }
+    }
+}
+
+// The layer's weights into LDS, rows padded to PSTR elements.
+__device__ __forceinline__ void stage_weights(const bf16 *__restrict__ wl, bf16 *__restrict__ sw)
+{
+    for (int q = threadIdx.x; q < 9 * C * 4; q += BX) {
+        const int row = q >> 2, ch = q & 3;
+        *reinterpret_cast<uint4 *>(sw + row * PSTR + ch * 8) = *reinterpret_cast<const uint4 *>(wl + row * C + ch * 8);
+    }
+}
+
 template <bool MIRROR>
 __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wl,
                                                     bf16 *__restrict__ out, const bf16 *__restrict__ mask, int B,
@@ -180,19 +256,13 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
 {
     __shared__ __align__(16) bf16 sw[9 * C * PSTR];
     __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int q = tid; q < 9 * C * 4; q += BX) {
-        const int row = q >> 2, ch = q & 3;
-        *reinterpret_cast<uint4 *>(sw + row * PSTR + ch * 8) = *reinterpret_cast<const uint4 *>(wl + row * C + ch * 8);
-    }
+    const int tid = threadIdx.x;
+    stage_weights(wl, sw);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
     const int ntiles = B * tiles_h * tiles_w;  // < 2^31: at most 2^31 pixels
-    const int n = lane & 31, kg = lane >> 5;
     uint4 reg[PPER];
     if ((int)blockIdx.x < ntiles) patch_load(in, blockIdx.x, tiles_w, tiles_h, H, W, reg);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
-        const int i0 = th * TROWS, j0 = tw * TPX;
         __syncthreads();  // the previous tile's LDS reads are done (first pass: weights stored)
 #pragma unroll
         for (int u = 0; u < PPER; ++u) {
@@ -205,47 +275,61 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
         __syncthreads();
         // the next tile's patch loads fly while this tile's matrix products run
         if (tile + (int)gridDim.x < ntiles) patch_load(in, tile + gridDim.x, tiles_w, tiles_h, H, W, reg);
-        f32x16 acc0 = {}, acc1 = {};
-#pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int pr = wv + 1 + tap_dy(t, MIRROR), pc = n + 1 + tap_dx(t, MIRROR);
-#pragma unroll
-            for (int c16 = 0; c16 < 2; ++c16) {
-                const int k0 = c16 * 16 + kg * 8;
-                bf16x8 av, b0, b1;
-                __builtin_memcpy(&av, sw + (t * C + n) * PSTR + k0, 16);
-                __builtin_memcpy(&b0, sp + (pr * PCOLS + pc) * PSTR + k0, 16);
-                __builtin_memcpy(&b1, sp + (pr * PCOLS + pc + 32) * PSTR + k0, 16);
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
-            }
+        conv32_tile<MIRROR>(sw, sp, tile, tiles_w, tiles_h, H, W, out, mask);
+    }
+}
+
+// Layers 1 and 2 in one pass (inference: the layer-1 activations are not kept).  Per tile
+// the block stages the input x of the patch's neighbourhood ((PROWS + 2) x (PCOLS + 2)
+// pixels, rounded as the first layer's input), computes layer 1 for the PROWS x PCOLS
+// patch pixels with l1_pixel straight into the patch buffer (zero outside the image, the
+// second layer's zero padding), then runs the second layer's matrix products as
+// conv32_kernel does.  The patch holds exactly the values l1_fwd_kernel would have
+// stored, so the output equals l1_fwd_kernel followed by conv32_kernel bit for bit, with
+// the 64-byte-per-pixel layer-1 activations never written to or read from memory.
+constexpr int XROWS = PROWS + 2, XCOLS = PCOLS + 2;
+template <typename TX>
+__global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, int ldx, double scale,
+                                                    const float *__restrict__ w1s, const bf16 *__restrict__ wl,
+                                                    bf16 *__restrict__ out, int B, int H, int W)
+{
+    __shared__ __align__(16) bf16 sw[9 * C * PSTR];
+    __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
+    __shared__ float sx[XROWS * XCOLS];
+    const int tid = threadIdx.x;
+    stage_weights(wl, sw);
+    const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
+    const int ntiles = B * tiles_h * tiles_w;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
+        const int i0 = th * TROWS, j0 = tw * TPX;
+        __syncthreads();  // the previous tile's reads of sx and sp are done
+        for (int q = tid; q < XROWS * XCOLS; q += BX) {
+            const int ii = i0 - 2 + q / XCOLS, jj = j0 - 2 + q % XCOLS;
+            float v = 0.0f;
+            if (ii >= 0 && ii < H && jj >= 0 && jj < W) v = l1_input(x[((long long)b * H + ii) * ldx + jj], scale);
+            sx[q] = v;
         }
-        const int i = i0 + wv;
-        if (i >= H) continue;
+        __syncthreads();
+        for (int q = tid; q < PROWS * PCOLS; q += BX) {
+            const int pr = q / PCOLS, pc = q % PCOLS;
+            const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
+            unsigned pk[C / 2];
+            if (ii >= 0 && ii < H && jj >= 0 && jj < W) {
+                float xv[9];
 #pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            const int j = j0 + half * 32 + n;
-            if (j >= W) continue;
-            const f32x16 &acc = half ? acc1 : acc0;
-            const long long p = ((long long)b * H + i) * W + j;
-            // lane holds output channels 8g + 4 kg + e (e = 0..3) of pixel j in acc[4g + e]
+                for (int t = 0; t < 9; ++t) xv[t] = sx[(pr + 1 + tap_dy(t, false)) * XCOLS + (pc + 1 + tap_dx(t, false))];
+                l1_pixel(xv, w1s, pk);
+            } else {
 #pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int co = 8 * g + 4 * kg;
-                unsigned short v[4];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    float a = acc[4 * g + e];
-                    if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
-                    else a = relu(a);
-                    v[e] = f32_to_bf16_rne(a);
-                }
-                uint2 pk;
-                pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
-                pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
-                *reinterpret_cast<uint2 *>(out + p * C + co) = pk;
+                for (int k = 0; k < C / 2; ++k) pk[k] = 0u;
             }
+            uint4 *dst = reinterpret_cast<uint4 *>(sp + q * PSTR);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) dst[k] = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]);
         }
+        __syncthreads();
+        conv32_tile<false>(sw, sp, tile, tiles_w, tiles_h, H, W, out, nullptr);
     }
 }
 
@@ -898,6 +982,28 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
     return hipGetLastError();
 }
 
+// Inference: y = N(x * scale) as net_forward computes it, layers 1 and 2 fused (conv12_kernel),
+// so the layer-1 activations never reach memory; the hidden activations are not kept.
+hipError_t net_infer_forward(NetState &s, int xdt, const void *x, int ldx, double scale, float *y, int ldy, int B,
+                             int H, int W, hipStream_t st)
+{
+    const long long N = (long long)B * H * W;
+    hipError_t e = net_workspace(s, N);
+    if (e != hipSuccess) return e;
+    const unsigned cb = conv_blocks(B, H, W);
+    if (xdt == F64)
+        hipLaunchKernelGGL(conv12_kernel<double>, dim3(cb), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1s,
+                           s.nw.w2f, s.a2, B, H, W);
+    else
+        hipLaunchKernelGGL(conv12_kernel<float>, dim3(cb), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1s,
+                           s.nw.w2f, s.a2, B, H, W);
+    hipLaunchKernelGGL(conv32_kernel<false>, dim3(cb), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3, (const bf16 *)nullptr,
+                       B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(thin_blocks(B, H, W)), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
+    s.last_pixels = 0;  // the layer-1 activations of this pass were never stored
+    return hipGetLastError();
+}
+
 // Forward, loss and backward on compact FP32 x and t; gradient into s.g, loss into *loss.
 hipError_t net_gradient(NetState &s, const float *x, const float *t, int B, int H, int W, int loss,
                         double *loss_out, hipStream_t st)
@@ -1003,7 +1109,7 @@ namespace px {
 
 hipError_t net_infer(px_net *net, const double *r, int ld_r, int n, double scale, float *y, int ld_y, hipStream_t s)
 {
-    return net_forward(net->s, F64, r, ld_r, scale, y, ld_y, 1, n, n, s);
+    return net_infer_forward(net->s, F64, r, ld_r, scale, y, ld_y, 1, n, n, s);
 }
 
 int net_device(const px_net *net) { return net->device; }
@@ -1124,6 +1230,21 @@ int px_net_adam(px_net *net, float lr, void *stream)
     if (st) return st;
     hipError_t e = px::net_adam(net->s, lr, (hipStream_t)stream);
     return e == hipSuccess ? PX_OK : hip_err(e, "Adam launch");
+}
+
+int px_net_infer(px_net *net, const void *x, int x_dtype, int ldx, int batch, int H, int W, double x_scale, float *y,
+                 int ldy, void *stream)
+{
+    if (!net || !x || !y) return set_error(PX_EINVAL, "net, x or y is NULL");
+    if (x_dtype != PX_F64 && x_dtype != PX_F32) return set_error(PX_EINVAL, "x_dtype must be PX_F64 or PX_F32");
+    int st = check_images(batch, H, W);
+    if (st) return st;
+    if (ldx < W || ldy < W) return set_error(PX_EINVAL, "ldx and ldy must be >= W");
+    if (!std::isfinite(x_scale)) return set_error(PX_EINVAL, "x_scale must be finite");
+    if ((st = use_device(net))) return st;
+    hipError_t e = px::net_infer_forward(net->s, x_dtype, x, ldx, x_scale, y, ldy, batch, H, W, (hipStream_t)stream);
+    if (e == hipErrorOutOfMemory) return set_error(PX_ENOMEM, "network workspace allocation failed");
+    return e == hipSuccess ? PX_OK : hip_err(e, "network inference launch");
 }
 
 int px_net_activation(px_net *net, int layer, uint16_t *out, void *stream)

@@ -91,6 +91,30 @@ def test_forward_layers_match_oracle(B, Hh, Wd):
     net.close()
 
 
+@pytest.mark.parametrize("B,Hh,Wd,dt,scale", [(2, 37, 45, "f32", 1.0), (1, 64, 96, "f64", 0.37), (1, 5, 3, "f32", 1.0),
+                                               (3, 33, 131, "f64", 2.5), (1, 300, 257, "f32", 1.0)])
+def test_inference_equals_forward_bitwise(B, Hh, Wd, dt, scale):
+    """px_net_infer (layer 1 computed inside the first convolution's patch staging) gives
+    px_net_forward's output bit for bit, on ragged shapes (partial tiles in both
+    directions), several images, FP64 input with a scale; and leaves no activations."""
+    H.require_gpu()
+    w = W.net_initial_weights(41)
+    x = W.rng(42).standard_normal((B, Hh, Wd + 3)) * 2.0
+    net = px.Net(w)
+    xd = torch.from_numpy(x if dt == "f64" else x.astype(np.float32)).cuda()
+    y1 = torch.full((B, Hh, Wd), 7.0, dtype=torch.float32, device="cuda")
+    y2 = torch.full((B, Hh, Wd), -7.0, dtype=torch.float32, device="cuda")
+    print(f"case: infer vs forward B={B} H={Hh} W={Wd} {dt} scale={scale}", flush=True)
+    net.forward(xd[:, :, :Wd], y1, x_scale=scale)
+    net.forward(xd[:, :, :Wd], y2, x_scale=scale, infer=True)
+    torch.cuda.synchronize()
+    assert torch.equal(y1.view(torch.int32), y2.view(torch.int32))
+    out = torch.empty((B * Hh * Wd, 32), dtype=torch.int16, device="cuda")
+    with pytest.raises(px.ProtoxError):
+        net.activation(1, out)
+    net.close()
+
+
 def test_forward_fp64_input_and_scale():
     """FP64 input scaled by x_scale is rounded FP64 -> FP32 -> BF16, as the oracle's
     bf16_round of the FP64 product does."""

@@ -57,6 +57,11 @@ def test_forward_1024_every_tile_matches_oracle():
     mag = onet.conv3x3(np.abs(a3), np.abs(W4))[..., 0]
     got = y.cpu().numpy().astype(np.float64)[0]
     assert np.all(np.abs(got - ref[0]) <= gamma32(288) * mag[0] + 1e-30)
+    # inference (layers 1 and 2 fused, every block looping over its tiles) gives the same bits
+    y2 = torch.empty_like(y)
+    net.forward(xd, y2, infer=True)
+    torch.cuda.synchronize()
+    assert torch.equal(y.view(torch.int32), y2.view(torch.int32))
     net.close()
 
 
