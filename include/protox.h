@@ -111,10 +111,11 @@ int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
  * Autotuner: times the fused relaxation on the caller's buffers for every
  * sweeps-per-launch k in 1..8 and a list of tile heights (fastest of five
  * single launches each), re-times the four best as runs of 24 launches that
- * each read the previous one's output (as a sweep loop runs them), and
- * remembers the fastest (k, rows) of that second pass in ctx for this
- * (dtype, n, ld), together with the tile height for that k's launches that
- * also take the residual norms (fastest of three launches per height).  Later
+ * each read the previous one's output (as a sweep loop runs them), gives the
+ * two best of those a tile height for their launches that also take the
+ * residual norms (fastest of three launches per height), times both as whole
+ * calls (24 launches, the last with norms) and remembers the faster in ctx for
+ * this (dtype, n, ld).  Later
  * calls with tblock == 0 on such a grid use them (explicit tblock or
  * px_ctx_set_tile_rows override them).  phi_in is only read; phi_out is
  * overwritten with scratch iterates; f as in px_relax_fused.  Allocates the

@@ -200,7 +200,7 @@ Partials partials(px_ctx *ctx) { return Partials{ctx->pmax, ctx->psum}; }
 // last launch writes dst.  src is only read.  tmp may be NULL when one launch.
 int run_sweeps(px_ctx *ctx, int dtype, const void *src, void *dst, void *tmp, int n, int ld,
                const void *f, int ld_f, double h, double lambda, int nsweeps, int k, int bc,
-               int resmode, double *norms, hipStream_t s, int forced_rows = 0)
+               int resmode, double *norms, hipStream_t s, int forced_rows = 0, int forced_rows_norm = 0)
 {
     const int L = (nsweeps + k - 1) / k;
     const double c = 1.0 / (h * h);
@@ -223,7 +223,8 @@ int run_sweeps(px_ctx *ctx, int dtype, const void *src, void *dst, void *tmp, in
         a.bc = bc;
         a.sweeps = ks;
         a.resmode = (i == L - 1) ? resmode : RES_NONE;
-        a.rows = forced_rows > 0 ? forced_rows : pick_rows(ctx, dtype, n, ld, ks, a.resmode);
+        const int forced = (a.resmode != RES_NONE && forced_rows_norm > 0) ? forced_rows_norm : forced_rows;
+        a.rows = forced > 0 ? forced : pick_rows(ctx, dtype, n, ld, ks, a.resmode);
         a.part = partials(ctx);
         if (a.resmode != RES_NONE) {
             int st = ensure_partials(ctx, (size_t)relax_num_waves(dtype, n, ks, a.resmode, a.rows));
@@ -605,42 +606,78 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
             g2[i] = std::max(g2[i], g);
         }
     }
-    int bi = 0;
-    for (int i = 1; i < TOP; ++i)
-        if (g2[i] > g2[bi]) bi = i;
-    const int bk = top[bi].k, br = top[bi].rows;
-    const double bg = g2[bi];
-    // third pass: the tile height of the winner's launches that also take the norms (their
+    // the two best of the second pass go on
+    int order[TOP];
+    for (int i = 0; i < TOP; ++i) order[i] = i;
+    std::sort(order, order + TOP, [&](int a, int b) { return g2[a] > g2[b]; });
+    constexpr int FIN = 2;
+    int rn[FIN] = {0, 0};
+    // third pass: for each, the tile height of its launches that also take the norms (their
     // pipeline holds one more level, the residual's, so they favour other heights): the
-    // fastest of three single launches per candidate
-    int brn = 0;
-    if (!err && bk > 0) err = ensure_norms(ctx);
-    float best_norm = 0.f;
-    for (int rows : ROWS) {
-        if (err || rows > std::max(8, n + 2)) break;
-        if ((err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, bk, bk, bc, RES_FINAL,
-                              ctx->norms_dev, s, rows)))
-            break;
-        for (int rep = 0; rep < 3 && !err; ++rep) {
+    // fastest of three single launches per height
+    if (!err) err = ensure_norms(ctx);
+    for (int c = 0; c < FIN && !err; ++c) {
+        const int kc = top[order[c]].k;
+        if (kc == 0) continue;
+        if (c == 1 && kc == top[order[0]].k) {
+            rn[1] = rn[0];
+            continue;
+        }
+        float best_norm = 0.f;
+        for (int rows : ROWS) {
+            if (err || rows > std::max(8, n + 2)) break;
+            if ((err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, kc, kc, bc,
+                                  RES_FINAL, ctx->norms_dev, s, rows)))
+                break;
+            for (int rep = 0; rep < 3 && !err; ++rep) {
+                hipError_t he = hipEventRecord(e0, s);
+                if (he == hipSuccess)
+                    err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, kc, kc, bc,
+                                     RES_FINAL, ctx->norms_dev, s, rows);
+                if (err) break;
+                if (he == hipSuccess) he = hipEventRecord(e1, s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                float one = 0.f;
+                if (he == hipSuccess) he = hipEventElapsedTime(&one, e0, e1);
+                if (he != hipSuccess) {
+                    err = hip_fail(he, "autotune timing");
+                    break;
+                }
+                if (rn[c] == 0 || one < best_norm) {
+                    best_norm = one;
+                    rn[c] = rows;
+                }
+            }
+        }
+    }
+    // final pass: each as a whole call makes it -- RUN launches from phi_in, each reading
+    // the previous output, the last one also taking the norms at its own height -- fastest
+    // of three
+    double g4[FIN] = {0.0, 0.0};
+    for (int round = 0; round < ROUNDS && !err; ++round) {
+        for (int c = 0; c < FIN && !err; ++c) {
+            const Cand &cd = top[order[c]];
+            if (cd.k == 0) continue;
             hipError_t he = hipEventRecord(e0, s);
             if (he == hipSuccess)
-                err = run_sweeps(ctx, dtype, phi_in, phi_out, nullptr, n, ld, f, ld_f, h, lambda, bk, bk, bc,
-                                 RES_FINAL, ctx->norms_dev, s, rows);
+                err = run_sweeps(ctx, dtype, phi_in, phi_out, ctx->grid, n, ld, f, ld_f, h, lambda, RUN * cd.k, cd.k,
+                                 bc, RES_FINAL, ctx->norms_dev, s, cd.rows, rn[c]);
             if (err) break;
             if (he == hipSuccess) he = hipEventRecord(e1, s);
             if (he == hipSuccess) he = hipEventSynchronize(e1);
-            float one = 0.f;
-            if (he == hipSuccess) he = hipEventElapsedTime(&one, e0, e1);
+            float ms = 0.f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
             if (he != hipSuccess) {
                 err = hip_fail(he, "autotune timing");
                 break;
             }
-            if (brn == 0 || one < best_norm) {
-                best_norm = one;
-                brn = rows;
-            }
+            const double g = ms > 0.f ? RUN * cd.k * (double)n * n / (ms * 1e-3) / 1e9 : 0.0;
+            g4[c] = std::max(g4[c], g);
         }
     }
+    const int win = (g4[1] > g4[0]) ? 1 : 0;
+    const int bk = top[order[win]].k, br = top[order[win]].rows, brn = rn[win];
+    const double bg = g4[win];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err) return err;
