@@ -271,6 +271,26 @@ int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps,
                      int resmode, double *norms, px_ctx *ctx, void *stream);
 
 /*
+ * One domain split into boxes (Section IV: the grid is a union of boxes, each with its
+ * own ghost layer, and a sweep first fills every box's ghost cells from its neighbours'
+ * interiors, then relaxes each box on its own): nbx x nby boxes of n x n cells, boxes[i]
+ * for box row i / nbx and box column i % nbx (box (r, c) holds domain rows r*n .. r*n+n-1
+ * and columns c*n .. c*n+n-1), each with its own phi ((n+2) x ld, in place) and f; every
+ * box has the same n, h and lambda.  Every `exchange` sweeps (1..8; nsweeps must be a
+ * multiple) the ghost ring of every box is refreshed: a side facing another box takes that
+ * box's adjacent interior row or column; a side on the domain's edge takes -(adjacent
+ * interior) under PX_BC_DIRICHLET0, wraps onto the opposite edge's box under
+ * PX_BC_PERIODIC, and keeps its values under PX_BC_GHOST_FIXED.  Then every box relaxes
+ * `exchange` sweeps with its ghost ring held fixed (interface values lag by up to
+ * exchange - 1 sweeps).  With exchange = 1 the boxes' interiors equal px_relax_fused on the
+ * whole domain bit for bit.  Corners are not written.  Alignment and aliasing rules as for
+ * px_relax_batched; at most 65535 boxes.  Needs ctx (scratch of the batched relaxation).
+ */
+int px_relax_boxes(const px_problem *boxes, int nbx, int nby, int dtype, int nsweeps, int exchange, int bc,
+                   px_ctx *ctx, void *stream);
+
+/*
+ * Autotuner for batches: the tile rows of each problem size/*
  * Autotuner for batches: the tile rows of each problem size (the problems of that size
  * relaxed alone with the persistent kernel, 8 sweeps per launch, every candidate height),
  * then the sweeps per launch k in 1..8 for the whole batch.  Remembered in ctx for

@@ -214,6 +214,61 @@ def relax_sides(phi, f, n, h, lam, nsweeps, bcs, resmode=RES_FINAL, out=None):
     return out, float(norms[0]), float(norms[1])
 
 
+def exchange_boxes(phis, nbx, nby, n, bc=BC_DIRICHLET0):
+    """Section IV's copy between the boxes of one domain, in place: every box's ghost ring
+    (corners excepted) from its neighbours' adjacent interior rows and columns; on the
+    domain's edge -(adjacent interior) for DIRICHLET0, the opposite edge's box for PERIODIC,
+    unchanged for GHOST_FIXED.  phis: nbx * nby ghosted grids in box-row-major order (box
+    b covers domain rows (b // nbx) * n .. and columns (b % nbx) * n ..)."""
+    def neg(a):
+        return a ^ np.uint16(0x8000) if a.dtype == np.uint16 else -a
+    for b in range(nbx * nby):
+        bi, bj = divmod(b, nbx)
+        me = phis[b]
+        for side, (di, dj) in enumerate(((-1, 0), (1, 0), (0, -1), (0, 1))):
+            ni, nj = bi + di, bj + dj
+            if not (0 <= ni < nby and 0 <= nj < nbx):
+                if bc == BC_PERIODIC:
+                    ni, nj = ni % nby, nj % nbx
+                else:
+                    if bc == BC_DIRICHLET0:
+                        if side == 0:
+                            me[0, 1:n + 1] = neg(me[1, 1:n + 1])
+                        elif side == 1:
+                            me[n + 1, 1:n + 1] = neg(me[n, 1:n + 1])
+                        elif side == 2:
+                            me[1:n + 1, 0] = neg(me[1:n + 1, 1])
+                        else:
+                            me[1:n + 1, n + 1] = neg(me[1:n + 1, n])
+                    continue
+            nb = phis[ni * nbx + nj]
+            if side == 0:
+                me[0, 1:n + 1] = nb[n, 1:n + 1]
+            elif side == 1:
+                me[n + 1, 1:n + 1] = nb[1, 1:n + 1]
+            elif side == 2:
+                me[1:n + 1, 0] = nb[1:n + 1, n]
+            else:
+                me[1:n + 1, n + 1] = nb[1:n + 1, 1]
+
+
+def relax_boxes(phis, fs, nbx, nby, n, h, lam, nsweeps, exchange=1, bc=BC_DIRICHLET0):
+    """A domain of boxes relaxed as the paper's Algorithm runs on Proto boxes: every
+    `exchange` sweeps the ghost rings are exchanged (exchange_boxes), then every box
+    relaxes `exchange` sweeps on its own with its ghost ring held (GHOST_FIXED).  Returns new
+    grids (corners copied from the inputs)."""
+    assert nsweeps % exchange == 0
+    cur = [np.array(p, copy=True) for p in phis]
+    for _ in range(nsweeps // exchange):
+        exchange_boxes(cur, nbx, nby, n, bc)
+        nxt = []
+        for p, f in zip(cur, fs):
+            out, _, _ = relax(p, f, n, h, lam, exchange, bc=BC_GHOST_FIXED, resmode=RES_NONE, out=p.copy())
+            nxt.append(out)
+        cur = nxt
+    return cur
+
+
 def refine(phi, f, n, h, lam, lowp, k_in, max_outer, rtol, bc=BC_DIRICHLET0):
     """FP64 iterative refinement around k_in low-precision sweeps (lowp 1=FP32, 2=BF16).
 

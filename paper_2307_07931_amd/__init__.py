@@ -78,7 +78,7 @@ EXPORTS = ("px_ctx_create", "px_ctx_destroy", "px_ctx_reserve", "px_ctx_set_tile
            "px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
            "px_net_forward", "px_net_loss_grad", "px_net_adam", "px_net_activation",
            "px_net_make_pair", "px_correction_step", "px_solve_learned", "px_relax_fused_noalloc",
-           "px_net_infer")
+           "px_net_infer", "px_relax_boxes")
 
 _lib = None
 
@@ -110,6 +110,7 @@ def lib() -> ctypes.CDLL:
     L.px_autotune.argtypes = [P, P, I, I, I, P, I, I, P, P, ctypes.POINTER(I), ctypes.POINTER(I),
                               ctypes.POINTER(D)]
     L.px_relax_batched.argtypes = [ctypes.POINTER(_Problem), I, I, I, I, I, I, P, P, P]
+    L.px_relax_boxes.argtypes = [ctypes.POINTER(_Problem), I, I, I, I, I, I, P, P]
     L.px_autotune_batched.argtypes = [ctypes.POINTER(_Problem), I, I, I, P, P, ctypes.POINTER(I)]
     L.px_solve_batched.argtypes = [ctypes.POINTER(_Problem), I, ctypes.POINTER(_SolveOpts),
                                    ctypes.POINTER(_SolveStats), P, P]
@@ -130,7 +131,7 @@ def lib() -> ctypes.CDLL:
     for nm in ("px_autotune_batched", "px_net_create", "px_net_destroy", "px_net_set_weights", "px_net_get_weights",
                "px_net_forward", "px_net_infer", "px_net_loss_grad", "px_net_adam", "px_net_activation",
                "px_net_make_pair", "px_correction_step", "px_solve_learned",
-               "px_relax_batched", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
+               "px_relax_batched", "px_relax_boxes", "px_solve_batched", "px_ctx_create", "px_ctx_destroy",
                "px_ctx_reserve", "px_ctx_set_tile_rows", "px_autotune",
                "px_apply_stencil", "px_residual", "px_jacobi_update", "px_relax_fused", "px_solve"):
         getattr(L, nm).restype = I
@@ -364,6 +365,15 @@ def relax_batched(items, nsweeps, ctx: Context, tblock=0, bc=BC_DIRICHLET0, resm
     arr, dt = _problems(items)
     _check(lib().px_relax_batched(arr, len(items), _DTYPE_CODE[dt], int(nsweeps), int(tblock), int(bc),
                                   int(resmode), _ptr(norms), ctx.handle, _stream_handle(stream)))
+
+
+def relax_boxes(items, nbx, nby, nsweeps, ctx: Context, exchange=1, bc=BC_DIRICHLET0, stream=None):
+    """One domain of nbx x nby boxes (items in box-row-major order, each (phi, f, n, h, lam)
+    with the same n, h and lam): ghost rings refreshed from the neighbouring boxes every
+    `exchange` sweeps, then each box relaxed with fixed ghosts; in place."""
+    arr, dt = _problems(items)
+    _check(lib().px_relax_boxes(arr, int(nbx), int(nby), _DTYPE_CODE[dt], int(nsweeps), int(exchange), int(bc), ctx.handle,
+                                _stream_handle(stream)))
 
 
 def autotune_batched(items, ctx: Context, bc=BC_DIRICHLET0, stream=None) -> int:

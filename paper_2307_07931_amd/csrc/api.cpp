@@ -948,6 +948,31 @@ int px_relax_batched(const px_problem *probs, int nprob, int dtype, int nsweeps,
     return st ? fail(st, "%s", err) : PX_OK;
 }
 
+int px_relax_boxes(const px_problem *boxes, int nbx, int nby, int dtype, int nsweeps, int exchange, int bc,
+                   px_ctx *ctx, void *stream)
+{
+    if (nbx < 1 || nby < 1 || (long long)nbx * nby > 65535)
+        return fail(PX_EINVAL, "box layout %d x %d outside 1..65535 boxes", nbx, nby);
+    std::vector<BatchProblem> bp;
+    int st = check_batch(boxes, nbx * nby, dtype, bp);
+    if (st) return st;
+    for (int b = 1; b < nbx * nby; ++b)
+        if (bp[b].n != bp[0].n || bp[b].h != bp[0].h || bp[b].lambda != bp[0].lambda)
+            return fail(PX_EINVAL, "box %d: every box of a domain needs the same n, h and lambda", b);
+    if (nsweeps < 0) return fail(PX_EINVAL, "nsweeps = %d < 0", nsweeps);
+    if (exchange < 1 || exchange > 8) return fail(PX_EINVAL, "exchange = %d outside [1, 8]", exchange);
+    if (nsweeps % exchange) return fail(PX_EINVAL, "nsweeps = %d is not a multiple of exchange = %d", nsweeps, exchange);
+    if (!valid_bc(bc)) return fail(PX_EINVAL, "unknown bc %d", bc);
+    if (!ctx) return fail(PX_EINVAL, "ctx is NULL");
+    if ((st = set_device(ctx))) return st;
+    if (!ctx->batch) ctx->batch = new (std::nothrow) BatchWork();
+    if (!ctx->batch) return fail(PX_ENOMEM, "out of host memory");
+    char err[256] = "";
+    st = batch_relax_boxes(*ctx->batch, dtype, bp.data(), nbx, nby, nsweeps, exchange, bc, ctx->tile_rows,
+                           (hipStream_t)stream, err, sizeof err);
+    return st ? fail(st, "%s", err) : PX_OK;
+}
+
 int px_autotune_batched(const px_problem *probs, int nprob, int dtype, int bc, px_ctx *ctx, void *stream, int *best_k)
 {
     std::vector<BatchProblem> bp;

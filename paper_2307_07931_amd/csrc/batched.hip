@@ -340,6 +340,7 @@ int BatchWork::rows_for(int dtype, int n, int k, int forced) const
 BatchWork::~BatchWork()
 {
     if (mem) (void)hipFree(mem);
+    if (boxmem) (void)hipFree(boxmem);
     if (graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
     if (stream) (void)hipStreamDestroy(static_cast<hipStream_t>(stream));
 }
@@ -465,6 +466,107 @@ int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, i
         e = copy_back_launch(dtype, dev_ptr<const KArgs>(base, shapes[seq[0]].args_off[0]), nprob, s);
     if (e != hipSuccess) {
         snprintf(err, errlen, "batched relaxation: %s", hipGetErrorString(e));
+        return PX_EHIP;
+    }
+    return PX_OK;
+}
+
+// ------------------------------------------------------------ multi-box domains
+
+namespace {
+
+struct BoxDesc {
+    void *phi;
+    int ld, pad;
+};
+
+template <typename T> __device__ __forceinline__ T negated(T x) { return -x; }
+template <> __device__ __forceinline__ bf16 negated(bf16 x) { return bf16{(unsigned short)(x.bits ^ 0x8000u)}; }
+
+// One ghost cell per thread: blockIdx.z = box, blockIdx.y = side (0 north: row 0, 1 south:
+// row n + 1, 2 west: column 0, 3 east: column n + 1), index 1..n along the side.  A side
+// facing another box copies that box's adjacent interior row or column; a side on the
+// domain edge takes -(adjacent interior) under DIRICHLET0, wraps onto the opposite box
+// under PERIODIC, and is left alone under GHOST_FIXED.  Only ghost cells are written and
+// only interior cells read, so the boxes can be refreshed all at once.  Corners are not
+// touched (the 5-point stencil does not read them).
+template <typename T>
+__global__ __launch_bounds__(BX) void box_exchange_kernel(const BoxDesc *__restrict__ boxes, int nbx, int nby, int n,
+                                                          int bc)
+{
+    const int idx = (int)(blockIdx.x * BX + threadIdx.x) + 1;
+    if (idx > n) return;
+    const int side = (int)blockIdx.y, b = (int)blockIdx.z;
+    const int bi = b / nbx, bj = b % nbx;
+    T *me = static_cast<T *>(boxes[b].phi);
+    const size_t ld = (size_t)boxes[b].ld;
+    int ni = bi, nj = bj;  // the box across this side
+    if (side == 0) ni = bi - 1;
+    else if (side == 1) ni = bi + 1;
+    else if (side == 2) nj = bj - 1;
+    else nj = bj + 1;
+    const bool inside = ni >= 0 && ni < nby && nj >= 0 && nj < nbx;
+    // ghost position and the interior cell it mirrors, in this box
+    size_t g, a;
+    if (side == 0) { g = (size_t)idx; a = ld + idx; }
+    else if (side == 1) { g = (size_t)(n + 1) * ld + idx; a = (size_t)n * ld + idx; }
+    else if (side == 2) { g = (size_t)idx * ld; a = (size_t)idx * ld + 1; }
+    else { g = (size_t)idx * ld + n + 1; a = (size_t)idx * ld + n; }
+    if (!inside && bc == PERIODIC) {
+        ni = (ni + nby) % nby;
+        nj = (nj + nbx) % nbx;
+    } else if (!inside) {
+        if (bc == DIRICHLET0) me[g] = negated(me[a]);
+        return;
+    }
+    const T *nb = static_cast<const T *>(boxes[ni * nbx + nj].phi);
+    const size_t ldn = (size_t)boxes[ni * nbx + nj].ld;
+    size_t src;  // the neighbour's interior cell next to this ghost
+    if (side == 0) src = (size_t)n * ldn + idx;
+    else if (side == 1) src = ldn + idx;
+    else if (side == 2) src = (size_t)idx * ldn + n;
+    else src = (size_t)idx * ldn + 1;
+    me[g] = nb[src];
+}
+
+}  // namespace
+
+int batch_relax_boxes(BatchWork &w, int dtype, const BatchProblem *probs, int nbx, int nby, int nsweeps, int exchange,
+                      int bc, int forced_rows, hipStream_t s, char *err, size_t errlen)
+{
+    const int nbox = nbx * nby, n = probs[0].n;
+    std::vector<BoxDesc> desc(nbox);
+    for (int b = 0; b < nbox; ++b) desc[b] = BoxDesc{probs[b].phi, probs[b].ld, 0};
+    const size_t need = sizeof(BoxDesc) * (size_t)nbox;
+    hipError_t e = hipSuccess;
+    if (w.boxbytes < need) {
+        if (w.boxmem) (void)hipFree(w.boxmem);
+        w.boxmem = nullptr;
+        w.boxbytes = 0;
+        if ((e = hipMalloc(&w.boxmem, need)) != hipSuccess) {
+            snprintf(err, errlen, "hipMalloc(%zu) for the box descriptors failed", need);
+            return PX_ENOMEM;
+        }
+        w.boxbytes = need;
+    }
+    e = hipMemcpyAsync(w.boxmem, desc.data(), need, hipMemcpyHostToDevice, s);
+    const dim3 grid((unsigned)((n + BX - 1) / BX), 4u, (unsigned)nbox);
+    for (int done = 0; done < nsweeps && e == hipSuccess; done += exchange) {
+        switch (dtype) {
+        case F64: hipLaunchKernelGGL(box_exchange_kernel<double>, grid, dim3(BX), 0, s,
+                                     static_cast<const BoxDesc *>(w.boxmem), nbx, nby, n, bc); break;
+        case F32: hipLaunchKernelGGL(box_exchange_kernel<float>, grid, dim3(BX), 0, s,
+                                     static_cast<const BoxDesc *>(w.boxmem), nbx, nby, n, bc); break;
+        default: hipLaunchKernelGGL(box_exchange_kernel<bf16>, grid, dim3(BX), 0, s,
+                                    static_cast<const BoxDesc *>(w.boxmem), nbx, nby, n, bc); break;
+        }
+        if ((e = hipGetLastError()) != hipSuccess) break;
+        const int st = batch_relax(w, dtype, probs, nbox, exchange, exchange, GHOST_FIXED, RES_NONE, nullptr,
+                                   forced_rows, s, err, errlen);
+        if (st) return st;
+    }
+    if (e != hipSuccess) {
+        snprintf(err, errlen, "box exchange: %s", hipGetErrorString(e));
         return PX_EHIP;
     }
     return PX_OK;

@@ -133,11 +133,19 @@ struct BatchWork {
     int tuned_k[3] = {0, 0, 0};
     std::vector<std::pair<int, int>> tuned_rows[3];
     int rows_for(int dtype, int n, int k, int forced) const;
+    // box descriptors of multi-box calls (batch_relax_boxes)
+    void *boxmem = nullptr;
+    size_t boxbytes = 0;
     ~BatchWork();
     hipError_t ensure(size_t need);
 };
 int batch_relax(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int nsweeps, int k, int bc,
                 int resmode, double *norms, int forced_rows, hipStream_t s, char *err, size_t errlen);
+// Boxes of one domain (px_relax_boxes): nbx x nby boxes of equal n in row-major order, in
+// place; every `exchange` sweeps the ghost rings are refreshed from the neighbouring boxes
+// (domain edges per bc), then every box relaxes `exchange` sweeps with fixed ghosts.
+int batch_relax_boxes(BatchWork &w, int dtype, const BatchProblem *probs, int nbx, int nby, int nsweeps, int exchange,
+                      int bc, int forced_rows, hipStream_t s, char *err, size_t errlen);
 // Autotuner of batched relaxation (see px_autotune_batched); relaxes the problems in place.
 int batch_autotune(BatchWork &w, int dtype, const BatchProblem *probs, int nprob, int bc, hipStream_t s,
                    int *best_k, char *err, size_t errlen);

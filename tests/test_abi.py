@@ -357,3 +357,19 @@ def test_correction_step_validation(ctx):
     assert run(h=0.0) == px.EINVAL
     assert run(r=FAKE + 64) == px.EALIAS
     assert run(d=FAKE + 64) == px.EALIAS
+
+
+def test_relax_boxes_validation(ctx):
+    """px_relax_boxes checks the layout, equal box sizes and the exchange period on the host."""
+    P = ctypes.c_void_p
+    L = px.lib()
+    arr = (px._Problem * 2)()
+    arr[0] = px._Problem(FAKE, FAKE2, 16, 18, 16, 1 / 32, 1e-5)
+    arr[1] = px._Problem(FAKE * 64, FAKE2 * 4, 16, 18, 16, 1 / 32, 1e-5)
+    assert L.px_relax_boxes(arr, 0, 2, px.F64, 4, 1, 0, ctx, None) == px.EINVAL      # layout
+    assert L.px_relax_boxes(arr, 2, 1, px.F64, 4, 3, 0, ctx, None) == px.EINVAL      # 4 % 3 != 0
+    assert L.px_relax_boxes(arr, 2, 1, px.F64, 4, 9, 0, ctx, None) == px.EINVAL      # exchange > 8
+    assert L.px_relax_boxes(arr, 2, 1, px.F64, 4, 1, 7, ctx, None) == px.EINVAL      # bc
+    arr[1] = px._Problem(FAKE * 64, FAKE2 * 4, 20, 22, 20, 1 / 32, 1e-5)
+    assert L.px_relax_boxes(arr, 2, 1, px.F64, 4, 1, 0, ctx, None) == px.EINVAL      # unequal n
+    assert "same n" in px.last_error()

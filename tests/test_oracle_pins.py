@@ -512,3 +512,100 @@ def test_residual_terms_are_the_norms_terms(dt):
     for t in terms:
         seq += t * t
     assert seq == 2.0 ** 54 and oracle.exact_sum_squares(terms) == 2.0 ** 54 + 4.0
+
+
+# ------------------------------------------------------------- box domains --
+
+def _split(grid, nbx, nby, n):
+    """A ghosted domain grid cut into ghosted boxes (each box's ghost ring from the domain)."""
+    return [np.ascontiguousarray(grid[bi * n:bi * n + n + 2, bj * n:bj * n + n + 2])
+            for bi in range(nby) for bj in range(nbx)]
+
+
+@pytest.mark.parametrize("bc", [oracle.BC_DIRICHLET0, oracle.BC_GHOST_FIXED, oracle.BC_PERIODIC])
+@pytest.mark.parametrize("nbx,nby", [(2, 2), (3, 1), (1, 2)])
+def test_boxes_with_exchange_every_sweep_equal_the_whole_domain(bc, nbx, nby):
+    """Section IV's boxes: exchanging the ghost layers before every sweep, then relaxing each
+    box with its ghosts held, is the Jacobi sweep of the whole domain -- bit for bit, for
+    each boundary rule (with fixed ghosts the domain's own ghost ring is what the boxes on
+    its edge hold)."""
+    n, N = 12, 9
+    Ny, Nx = nby * n, nbx * n
+    rng = np.random.default_rng(70 + 3 * nbx + nby)
+    dom = np.zeros((Ny + 2, Nx + 2))
+    dom[1:Ny + 1, 1:Nx + 1] = rng.uniform(-1, 1, (Ny, Nx))
+    dom[0, :] = rng.uniform(-1, 1, Nx + 2)
+    dom[Ny + 1, :] = rng.uniform(-1, 1, Nx + 2)
+    dom[:, 0] = rng.uniform(-1, 1, Ny + 2)
+    dom[:, Nx + 1] = rng.uniform(-1, 1, Ny + 2)
+    F = rng.uniform(-1, 1, (Ny, Nx))
+    if bc == oracle.BC_PERIODIC:
+        F -= F.mean()
+    h = 1.0 / Nx
+    lam = (2.0 / 3.0) * h * h / 4.0
+    # boxes on the domain's edge start with the domain's ghost ring there (what GHOST_FIXED
+    # keeps; the other rules overwrite it)
+    boxes = _split(dom, nbx, nby, n)
+    fs = [np.ascontiguousarray(F[bi * n:(bi + 1) * n, bj * n:(bj + 1) * n]) for bi in range(nby) for bj in range(nbx)]
+    got = oracle.relax_boxes(boxes, fs, nbx, nby, n, h, lam, N, exchange=1, bc=bc)
+    ref = _rect_reference(dom, F, Ny, Nx, h, lam, N, bc)
+    if Nx == Ny:
+        # the written-out rectangle sweep is the oracle's sweep on square domains
+        sq, _, _ = oracle.relax(dom, F, Ny, h, lam, N, bc=bc, resmode=oracle.RES_NONE)
+        assert np.array_equal(sq[1:Ny + 1, 1:Nx + 1], ref[1:Ny + 1, 1:Nx + 1])
+    for b, g in enumerate(got):
+        bi, bj = divmod(b, nbx)
+        want = ref[bi * n + 1:bi * n + n + 1, bj * n + 1:bj * n + n + 1]
+        assert np.array_equal(g[1:n + 1, 1:n + 1].view(np.int64), want.view(np.int64)), (b, bc)
+
+
+def _rect_reference(dom, F, Ny, Nx, h, lam, N, bc):
+    """N Jacobi sweeps of a rectangular domain: the three steps written out (ghosts per bc,
+    stencil in the paper's order, update into a separate array)."""
+    c = 1.0 / (h * h)
+    w = lam / (h * h)
+    phi = dom.copy()
+    for _ in range(N):
+        g = phi.copy()
+        if bc == oracle.BC_DIRICHLET0:
+            g[0, 1:Nx + 1] = -g[1, 1:Nx + 1]
+            g[Ny + 1, 1:Nx + 1] = -g[Ny, 1:Nx + 1]
+            g[1:Ny + 1, 0] = -g[1:Ny + 1, 1]
+            g[1:Ny + 1, Nx + 1] = -g[1:Ny + 1, Nx]
+        elif bc == oracle.BC_PERIODIC:
+            g[0, 1:Nx + 1] = g[Ny, 1:Nx + 1]
+            g[Ny + 1, 1:Nx + 1] = g[1, 1:Nx + 1]
+            g[1:Ny + 1, 0] = g[1:Ny + 1, Nx]
+            g[1:Ny + 1, Nx + 1] = g[1:Ny + 1, 1]
+        C = g[1:Ny + 1, 1:Nx + 1]
+        s = (((g[0:Ny, 1:Nx + 1] - 4.0 * C) + g[1:Ny + 1, 0:Nx]) + g[1:Ny + 1, 2:Nx + 2]) + g[2:Ny + 2, 1:Nx + 1]
+        new = phi.copy()
+        new[1:Ny + 1, 1:Nx + 1] = (C + w * s) - lam * F
+        phi = new
+    return phi
+
+
+def test_boxes_with_lagged_exchange_hold_interfaces_between_exchanges():
+    """Exchanging every k > 1 sweeps differs from the whole-domain sweep only through the
+    held interface values: the first sweep after an exchange is exact, and one box with
+    its ghost ring refreshed is exactly the fixed-ghost relaxation of that box."""
+    n = 10
+    rng = np.random.default_rng(80)
+    boxes = [np.zeros((n + 2, n + 2)) for _ in range(2)]
+    for b in boxes:
+        b[1:n + 1, 1:n + 1] = rng.uniform(-1, 1, (n, n))
+    fs = [rng.uniform(-1, 1, (n, n)) for _ in range(2)]
+    h = 1.0 / (2 * n)
+    lam = (2.0 / 3.0) * h * h / 4.0
+    one = oracle.relax_boxes(boxes, fs, 2, 1, n, h, lam, 1, exchange=1)
+    lagged = oracle.relax_boxes(boxes, fs, 2, 1, n, h, lam, 4, exchange=4)
+    exact4 = oracle.relax_boxes(boxes, fs, 2, 1, n, h, lam, 4, exchange=1)
+    # k = 4: every ghost (interface and domain edge) is held for sweeps 2..4, so a held value
+    # reaches 3 cells in; cells farther from every ghost see none of them
+    far = slice(4, n - 3 + 1)
+    for l4, e4 in zip(lagged, exact4):
+        assert np.array_equal(l4[far, far], e4[far, far])
+    assert not np.array_equal(lagged[0][1:n + 1, n], exact4[0][1:n + 1, n])  # next to the interface
+    # one sweep with a fresh exchange is the whole-domain sweep (same as exchange = 1)
+    first = oracle.relax_boxes(boxes, fs, 2, 1, n, h, lam, 1, exchange=1)
+    assert all(np.array_equal(a, b) for a, b in zip(one, first))
