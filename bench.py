@@ -708,6 +708,46 @@ def batched_workload(px, ctx, count=512):
     return out
 
 
+def boxes_workload(px, ctx):
+    """The domain of Section IV split into boxes: 256^2 cells as 4 x 4 boxes of 64^2 (the
+    paper's box and domain sizes), 100 sweeps, FP64, Dirichlet edges; ghost layers exchanged
+    before every sweep (bit-identical to the whole-domain sweep) or every 4 sweeps, against
+    one fused call on the whole 256^2 grid; and 8192^2 as 16 x 16 boxes of 512^2."""
+    import numpy as np
+    import torch
+    import workloads as W
+    out = {}
+    for nb, n, sweeps in ((4, 64, 100), (16, 512, 96)):
+        N = nb * n
+        h = 1.0 / N
+        lam = OMEGA * h * h / 4.0
+        F = W.uniform_rhs(N, 6)
+        items = []
+        for bi in range(nb):
+            for bj in range(nb):
+                phi = px.alloc_grid(n, torch.float64)
+                f = px.alloc_rhs(n, torch.float64)
+                f[:, :n] = torch.from_numpy(np.ascontiguousarray(F[bi * n:(bi + 1) * n, bj * n:(bj + 1) * n])).cuda()
+                items.append((phi, f, n, h, lam))
+        rec = {"domain": N, "boxes": f"{nb}x{nb} of {n}^2", "sweeps": sweeps}
+        for ex in (1, 4, 8):
+            if sweeps % ex:
+                continue
+            t = time_region(lambda: px.relax_boxes(items, nb, nb, sweeps, ctx, exchange=ex), reps=3, warmup=1) / 3
+            rec[f"exchange_{ex}_ms"] = round(t * 1e3, 3)
+            rec[f"exchange_{ex}_gcell_s"] = round(N * N * sweeps / t / 1e9, 2)
+        d = {"phi0": px.alloc_grid(N, torch.float64), "phi_out": px.alloc_grid(N, torch.float64),
+             "f": px.alloc_rhs(N, torch.float64), "n": N, "h": h, "lam": lam}
+        d["f"][:, :N] = torch.from_numpy(F).cuda()
+        t = time_region(lambda: px.relax_fused(d["phi0"], d["phi_out"], N, d["f"], h, lam, sweeps, ctx,
+                                               resmode=px.RES_NONE), reps=3, warmup=1) / 3
+        rec["whole_grid_ms"] = round(t * 1e3, 3)
+        rec["whole_grid_gcell_s"] = round(N * N * sweeps / t / 1e9, 2)
+        log(f"  boxes: {rec}")
+        out[f"{N}"] = rec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -719,7 +759,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 1 GiB device-to-device copy 5 times (the known-size kernel "
                          "that scales the FETCH_SIZE / WRITE_SIZE counters)")
-    ap.add_argument("--workload", choices=["relax", "mixed", "learned", "batched", "net"], default="relax",
+    ap.add_argument("--workload", choices=["relax", "mixed", "learned", "batched", "net", "boxes"], default="relax",
                     help="relax: the fused relaxation benchmark (default); mixed: mixed-precision "
                          "refinement against plain FP64 (time to tolerance); learned: the trained "
                          "correction network in the refinement loop; batched: 512 uneven problems")
@@ -764,9 +804,12 @@ def main():
         ctx.close()
         return
 
-    if args.workload in ("learned", "batched", "net"):
+    if args.workload in ("learned", "batched", "net", "boxes"):
         t0 = time.perf_counter()
-        if args.workload == "net":
+        if args.workload == "boxes":
+            res = boxes_workload(px, ctx)
+            value, unit = res["256"]["exchange_1_gcell_s"], "Gcell-updates/s (256^2 as 4 x 4 boxes of 64^2, exchange every sweep)"
+        elif args.workload == "net":
             res = net_workload(px)
             value, unit = res["infer_2048"]["gpix_s"], "Gpixel/s (network inference, 2048^2)"
         elif args.workload == "learned":

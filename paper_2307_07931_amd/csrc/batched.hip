@@ -340,7 +340,6 @@ int BatchWork::rows_for(int dtype, int n, int k, int forced) const
 BatchWork::~BatchWork()
 {
     if (mem) (void)hipFree(mem);
-    if (boxmem) (void)hipFree(boxmem);
     if (graph_exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(graph_exec));
     if (stream) (void)hipStreamDestroy(static_cast<hipStream_t>(stream));
 }
@@ -531,42 +530,88 @@ __global__ __launch_bounds__(BX) void box_exchange_kernel(const BoxDesc *__restr
 
 }  // namespace
 
+// Periods of `exchange` sweeps alternate between the boxes' own grids and scratch grids: one
+// exchange launch on the current grids, then one persistent relaxation launch into the
+// other set (fixed ghosts: each box's ghost ring travels with it); launch arguments and box
+// descriptors of both directions are uploaded once, and an odd number of periods ends with
+// one copy of every result back.
 int batch_relax_boxes(BatchWork &w, int dtype, const BatchProblem *probs, int nbx, int nby, int nsweeps, int exchange,
                       int bc, int forced_rows, hipStream_t s, char *err, size_t errlen)
 {
     const int nbox = nbx * nby, n = probs[0].n;
-    std::vector<BoxDesc> desc(nbox);
-    for (int b = 0; b < nbox; ++b) desc[b] = BoxDesc{probs[b].phi, probs[b].ld, 0};
-    const size_t need = sizeof(BoxDesc) * (size_t)nbox;
-    hipError_t e = hipSuccess;
-    if (w.boxbytes < need) {
-        if (w.boxmem) (void)hipFree(w.boxmem);
-        w.boxmem = nullptr;
-        w.boxbytes = 0;
-        if ((e = hipMalloc(&w.boxmem, need)) != hipSuccess) {
-            snprintf(err, errlen, "hipMalloc(%zu) for the box descriptors failed", need);
-            return PX_ENOMEM;
-        }
-        w.boxbytes = need;
+    const int periods = nsweeps / exchange;
+    if (periods == 0) return PX_OK;
+    const size_t es = (size_t)elem_size(dtype);
+    // layout: scratch grids | launch arguments [2][nbox] | tile offsets | box descriptors [2][nbox]
+    std::vector<size_t> tmp_off(nbox);
+    size_t off = 0;
+    for (int b = 0; b < nbox; ++b) {
+        tmp_off[b] = off;
+        off += round256((size_t)(n + 2) * probs[b].ld * es);
     }
-    e = hipMemcpyAsync(w.boxmem, desc.data(), need, hipMemcpyHostToDevice, s);
+    const size_t args_off[2] = {off, off + round256(sizeof(KArgs) * nbox)};
+    off = args_off[1] + round256(sizeof(KArgs) * nbox);
+    const size_t toff_off = off;
+    off += round256(sizeof(int) * (nbox + 1));
+    const size_t desc_off[2] = {off, off + round256(sizeof(BoxDesc) * nbox)};
+    off = desc_off[1] + round256(sizeof(BoxDesc) * nbox);
+    hipError_t e = w.ensure(off);
+    if (e != hipSuccess) {
+        snprintf(err, errlen, "hipMalloc(%zu) for the boxes failed", off);
+        return PX_ENOMEM;
+    }
+    char *base = static_cast<char *>(w.mem);
+    std::vector<KArgs> a[2];
+    std::vector<BoxDesc> d[2];
+    std::vector<int> toff(nbox + 1, 0);
+    for (int dir = 0; dir < 2; ++dir) {
+        a[dir].resize(nbox);
+        d[dir].resize(nbox);
+    }
+    for (int b = 0; b < nbox; ++b) {
+        const BatchProblem &q = probs[b];
+        void *tmp = base + tmp_off[b];
+        const int rows = w.rows_for(dtype, n, exchange, forced_rows);
+        a[0][b] = make_kargs(dtype, q.phi, tmp, q.f, n, q.ld, q.ld_f, q.h, q.lambda, GHOST_FIXED, exchange, RES_NONE,
+                             rows);
+        a[1][b] = make_kargs(dtype, tmp, q.phi, q.f, n, q.ld, q.ld_f, q.h, q.lambda, GHOST_FIXED, exchange, RES_NONE,
+                             rows);
+        toff[b + 1] = toff[b] + a[0][b].ntiles;
+        d[0][b] = BoxDesc{q.phi, q.ld, 0};
+        d[1][b] = BoxDesc{tmp, q.ld, 0};
+    }
+    for (int dir = 0; dir < 2 && e == hipSuccess; ++dir) {
+        e = hipMemcpyAsync(base + args_off[dir], a[dir].data(), sizeof(KArgs) * nbox, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(base + desc_off[dir], d[dir].data(), sizeof(BoxDesc) * nbox, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(base + toff_off, toff.data(), sizeof(int) * (nbox + 1), hipMemcpyHostToDevice, s);
+    BatchLaunchFn fn = pick_batch(dtype, exchange, RES_NONE);
+    if (!fn && e == hipSuccess) e = hipErrorInvalidValue;
     const dim3 grid((unsigned)((n + BX - 1) / BX), 4u, (unsigned)nbox);
-    for (int done = 0; done < nsweeps && e == hipSuccess; done += exchange) {
+    for (int i = 0; i < periods && e == hipSuccess; ++i) {
+        const BoxDesc *cur = dev_ptr<const BoxDesc>(base, desc_off[i % 2]);
         switch (dtype) {
-        case F64: hipLaunchKernelGGL(box_exchange_kernel<double>, grid, dim3(BX), 0, s,
-                                     static_cast<const BoxDesc *>(w.boxmem), nbx, nby, n, bc); break;
-        case F32: hipLaunchKernelGGL(box_exchange_kernel<float>, grid, dim3(BX), 0, s,
-                                     static_cast<const BoxDesc *>(w.boxmem), nbx, nby, n, bc); break;
-        default: hipLaunchKernelGGL(box_exchange_kernel<bf16>, grid, dim3(BX), 0, s,
-                                    static_cast<const BoxDesc *>(w.boxmem), nbx, nby, n, bc); break;
+        case F64: hipLaunchKernelGGL(box_exchange_kernel<double>, grid, dim3(BX), 0, s, cur, nbx, nby, n, bc); break;
+        case F32: hipLaunchKernelGGL(box_exchange_kernel<float>, grid, dim3(BX), 0, s, cur, nbx, nby, n, bc); break;
+        default: hipLaunchKernelGGL(box_exchange_kernel<bf16>, grid, dim3(BX), 0, s, cur, nbx, nby, n, bc); break;
         }
         if ((e = hipGetLastError()) != hipSuccess) break;
-        const int st = batch_relax(w, dtype, probs, nbox, exchange, exchange, GHOST_FIXED, RES_NONE, nullptr,
-                                   forced_rows, s, err, errlen);
-        if (st) return st;
+        BatchArgs ba;
+        ba.probs = dev_ptr<const KArgs>(base, args_off[i % 2]);
+        ba.tile_off = dev_ptr<const int>(base, toff_off);
+        ba.active = nullptr;
+        ba.nprob = nbox;
+        ba.total = toff[nbox];
+        ba.pmax = nullptr;  // no norms
+        ba.psum = nullptr;
+        e = fn(ba, s);
     }
+    if (e == hipSuccess && periods % 2 == 1)
+        e = copy_back_launch(dtype, dev_ptr<const KArgs>(base, args_off[0]), nbox, s);
     if (e != hipSuccess) {
-        snprintf(err, errlen, "box exchange: %s", hipGetErrorString(e));
+        snprintf(err, errlen, "box relaxation: %s", hipGetErrorString(e));
         return PX_EHIP;
     }
     return PX_OK;

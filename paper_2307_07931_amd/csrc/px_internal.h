@@ -133,9 +133,6 @@ struct BatchWork {
     int tuned_k[3] = {0, 0, 0};
     std::vector<std::pair<int, int>> tuned_rows[3];
     int rows_for(int dtype, int n, int k, int forced) const;
-    // box descriptors of multi-box calls (batch_relax_boxes)
-    void *boxmem = nullptr;
-    size_t boxbytes = 0;
     ~BatchWork();
     hipError_t ensure(size_t need);
 };
