@@ -333,53 +333,61 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
     }
 }
 
-// Layer 4: 32 channels -> 1, output FP32 into rows of ldy.  The a3 patch (6 x 66 pixels,
-// rows padded to PSTR elements) and the weights are staged in LDS; each thread reads its
-// 9 neighbours' 32 channels as 16-byte LDS loads.
+// Layer 4: 32 channels -> 1, output FP32 into rows of ldy.  Tiles of 4 rows x 64 pixels (the
+// convolution's), one pixel per thread; the a3 patch (6 x 66 pixels, rows padded to PSTR
+// elements) and the weights are staged in LDS, and each thread reads its 9 neighbours' 32
+// channels as 16-byte LDS loads.  Blocks loop over tiles with the next tile's patch loads
+// in flight while the current tile is summed, as the convolution does.
 __global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const float *__restrict__ w4s,
                                                     float *__restrict__ y, int ldy, int B, int H, int W)
 {
 #pragma clang fp contract(fast)
+    static_assert(LT_ROWS == TROWS && LT_PX == TPX, "layer 4 uses the convolution's tiles and patches");
     // weights tap-major in LDS: the 8 channels of one 16-byte activation read take their
     // 8 weights with two 16-byte reads (the same address in every lane)
     __shared__ __align__(16) float sw[9 * C];
-    __shared__ __align__(16) bf16 sp[(LT_ROWS + 2) * (LT_PX + 2) * PSTR];
-    const int tiles_w = (W + LT_PX - 1) / LT_PX, tiles_h = (H + LT_ROWS - 1) / LT_ROWS;
-    const int tw = (int)(blockIdx.x % tiles_w), th = (int)((blockIdx.x / tiles_w) % tiles_h);
-    const int b = (int)(blockIdx.x / ((unsigned)tiles_w * tiles_h));
-    const int i0 = th * LT_ROWS, j0 = tw * LT_PX;
+    __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
     for (int q = threadIdx.x; q < NW4; q += BX) sw[(q % 9) * C + q / 9] = w4s[q];
-    for (int q = threadIdx.x; q < (LT_ROWS + 2) * (LT_PX + 2) * 4; q += BX) {
-        const int ch = q & 3, pc = (q >> 2) % (LT_PX + 2), pr = (q >> 2) / (LT_PX + 2);
-        const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
-        uint4 v = make_uint4(0, 0, 0, 0);
-        if (ii >= 0 && ii < H && jj >= 0 && jj < W)
-            v = *reinterpret_cast<const uint4 *>(a3 + (((long long)b * H + ii) * W + jj) * C + ch * 8);
-        *reinterpret_cast<uint4 *>(sp + (pr * (LT_PX + 2) + pc) * PSTR + ch * 8) = v;
-    }
-    __syncthreads();
-    const int r = threadIdx.x / LT_PX, c = threadIdx.x % LT_PX;
-    const int i = i0 + r, j = j0 + c;
-    if (i >= H || j >= W) return;
-    float acc = 0.0f;
+    const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
+    const int ntiles = B * tiles_h * tiles_w;
+    const int r = threadIdx.x / TPX, c = threadIdx.x % TPX;
+    uint4 reg[PPER];
+    if ((int)blockIdx.x < ntiles) patch_load(a3, blockIdx.x, tiles_w, tiles_h, H, W, reg);
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
+        __syncthreads();  // the previous tile's LDS reads are done (first pass: weights stored)
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-        const bf16 *px = sp + ((r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))) * PSTR;
-#pragma unroll
-        for (int c8 = 0; c8 < 4; ++c8) {
-            const uint4 u = *reinterpret_cast<const uint4 *>(px + c8 * 8);
-            const float4 wa = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8);
-            const float4 wb = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8 + 4);
-            const float wv[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-            const unsigned wd[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                acc += wv[2 * e] * __uint_as_float(wd[e] << 16);
-                acc += wv[2 * e + 1] * __uint_as_float(wd[e] & 0xffff0000u);
+        for (int u = 0; u < PPER; ++u) {
+            const int q = (int)threadIdx.x + u * BX;
+            if (q < PCHUNKS) {
+                const int ch = q & 3, pix = q >> 2;
+                *reinterpret_cast<uint4 *>(sp + pix * PSTR + ch * 8) = reg[u];
             }
         }
+        __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) patch_load(a3, tile + gridDim.x, tiles_w, tiles_h, H, W, reg);
+        const int i = th * TROWS + r, j = tw * TPX + c;
+        if (i >= H || j >= W) continue;
+        float acc = 0.0f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const bf16 *px = sp + ((r + 1 + tap_dy(t, false)) * PCOLS + (c + 1 + tap_dx(t, false))) * PSTR;
+#pragma unroll
+            for (int c8 = 0; c8 < 4; ++c8) {
+                const uint4 u = *reinterpret_cast<const uint4 *>(px + c8 * 8);
+                const float4 wa = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8);
+                const float4 wb = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8 + 4);
+                const float wv[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
+                const unsigned wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    acc += wv[2 * e] * __uint_as_float(wd[e] << 16);
+                    acc += wv[2 * e + 1] * __uint_as_float(wd[e] & 0xffff0000u);
+                }
+            }
+        }
+        y[((long long)b * H + i) * ldy + j] = acc;
     }
-    y[((long long)b * H + i) * ldy + j] = acc;
 }
 
 // Fixed-order block reduction of one double per thread; thread 0 gets the total.
@@ -977,7 +985,7 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
                        (const bf16 *)nullptr, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
                        (const bf16 *)nullptr, B, H, W);
-    hipLaunchKernelGGL(l4_fwd_kernel, dim3(lt), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
     s.last_pixels = N;
     return hipGetLastError();
 }
@@ -999,7 +1007,7 @@ hipError_t net_infer_forward(NetState &s, int xdt, const void *x, int ldx, doubl
                            s.nw.w2f, s.a2, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(cb), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3, (const bf16 *)nullptr,
                        B, H, W);
-    hipLaunchKernelGGL(l4_fwd_kernel, dim3(thin_blocks(B, H, W)), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(cb), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
     s.last_pixels = 0;  // the layer-1 activations of this pass were never stored
     return hipGetLastError();
 }
