@@ -135,15 +135,31 @@ __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, in
     __syncthreads();
     const int r = threadIdx.x / LT_PX, c = threadIdx.x % LT_PX;
     const int i = i0 + r, j = j0 + c;
-    if (i >= H || j >= W) return;
-    float xv[9];
+    // each thread's 64-byte pixel goes through LDS so that every store instruction of a
+    // wave writes 1 KB of consecutive memory (16 pixels of one row) instead of 16 bytes
+    // from each of 64 pixels 64 bytes apart; pixel slots are padded to 80 bytes
+    constexpr int OSTR = 40;
+    __shared__ __align__(16) bf16 so[LT_ROWS * LT_PX * OSTR];
+    if (i < H && j < W) {
+        float xv[9];
 #pragma unroll
-    for (int t = 0; t < 9; ++t) xv[t] = sx[(r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))];
-    unsigned pk[C / 2];
-    l1_pixel(xv, sw, pk);
-    uint4 *dst = reinterpret_cast<uint4 *>(a1 + (((long long)b * H + i) * W + j) * C);
+        for (int t = 0; t < 9; ++t) xv[t] = sx[(r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))];
+        unsigned pk[C / 2];
+        l1_pixel(xv, sw, pk);
+        uint4 *st = reinterpret_cast<uint4 *>(so + threadIdx.x * OSTR);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dst[q] = make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
+        for (int q = 0; q < 4; ++q) st[q] = make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int chunk = q * BX + (int)threadIdx.x;  // 16-byte piece of the tile, row-major
+        const int row = chunk / (LT_PX * 4), px = (chunk / 4) % LT_PX, part = chunk % 4;
+        const int ii = i0 + row, jj = j0 + px;
+        if (ii < H && jj < W)
+            *reinterpret_cast<uint4 *>(a1 + (((long long)b * H + ii) * W + jj) * C + part * 8) =
+                *reinterpret_cast<const uint4 *>(so + (row * LT_PX + px) * OSTR + part * 8);
+    }
 }
 
 // 32 -> 32 convolution on the matrix cores, as an implicit GEMM per output tile.
@@ -187,11 +203,25 @@ __device__ __forceinline__ void patch_load(const bf16 *__restrict__ in, int tile
     }
 }
 
+// Orders a wave's LDS writes before its later LDS reads of other lanes' data (the LDS
+// serves one wave's instructions in order; this only stops the compiler moving them).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // The matrix products and the epilogue of one tile, its patch and the weights in LDS.
+// The epilogue goes through `so` (TROWS x TPX pixels, PSTR elements each; wave w uses
+// row w only): each lane leaves its results there and the wave then writes its row with
+// 16-byte stores of consecutive memory (1 KB per store instruction), where storing from
+// the accumulators directly scatters 8 bytes per lane over 32 pixels.  The backward's
+// ReLU mask comes in the same way, with coalesced loads.
 template <bool MIRROR>
-__device__ __forceinline__ void conv32_tile(const bf16 *__restrict__ sw, const bf16 *__restrict__ sp, int tile,
-                                            int tiles_w, int tiles_h, int H, int W, bf16 *__restrict__ out,
-                                            const bf16 *__restrict__ mask)
+__device__ __forceinline__ void conv32_tile(const bf16 *__restrict__ sw, const bf16 *__restrict__ sp,
+                                            bf16 *__restrict__ so, int tile, int tiles_w, int tiles_h, int H, int W,
+                                            bf16 *__restrict__ out, const bf16 *__restrict__ mask)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = lane & 31, kg = lane >> 5;
@@ -214,29 +244,54 @@ __device__ __forceinline__ void conv32_tile(const bf16 *__restrict__ sw, const b
     }
     const int i = i0 + wv;
     if (i >= H) return;
+    bf16 *row = so + wv * TPX * PSTR;
+    const long long p0 = ((long long)b * H + i) * W + j0;  // the row's first pixel
+    const int nvalid = min(TPX, W - j0);
+    if (MIRROR) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int chunk = q * 64 + lane, px = chunk >> 2, part = chunk & 3;
+            if (px < nvalid)
+                *reinterpret_cast<uint4 *>(row + px * PSTR + part * 8) =
+                    *reinterpret_cast<const uint4 *>(mask + (p0 + px) * C + part * 8);
+        }
+        wave_lds_sync();
+    }
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
-        const int j = j0 + half * 32 + n;
-        if (j >= W) continue;
         const f32x16 &acc = half ? acc1 : acc0;
-        const long long p = ((long long)b * H + i) * W + j;
-        // lane holds output channels 8g + 4 kg + e (e = 0..3) of pixel j in acc[4g + e]
+        // lane holds output channels 8g + 4 kg + e (e = 0..3) of pixel half*32 + n in acc[4g + e]
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
             const int co = 8 * g + 4 * kg;
+            uint2 *slot = reinterpret_cast<uint2 *>(row + (half * 32 + n) * PSTR + co);
+            uint2 mk = make_uint2(0, 0);
+            if (MIRROR) mk = *slot;  // this lane's own four mask values, overwritten below
             unsigned short v[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 float a = acc[4 * g + e];
-                if (MIRROR) a = bfv(mask[p * C + co + e]) > 0.0f ? a : 0.0f;
-                else a = relu(a);
+                if (MIRROR) {
+                    const unsigned mb = ((e < 2 ? mk.x : mk.y) >> (16 * (e & 1))) & 0xffffu;
+                    a = bf16_to_f32((unsigned short)mb) > 0.0f ? a : 0.0f;
+                } else {
+                    a = relu(a);
+                }
                 v[e] = f32_to_bf16_rne(a);
             }
             uint2 pk;
             pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
             pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
-            *reinterpret_cast<uint2 *>(out + p * C + co) = pk;
+            *slot = pk;
         }
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int chunk = q * 64 + lane, px = chunk >> 2, part = chunk & 3;
+        if (px < nvalid)
+            *reinterpret_cast<uint4 *>(out + (p0 + px) * C + part * 8) =
+                *reinterpret_cast<const uint4 *>(row + px * PSTR + part * 8);
     }
 }
 
@@ -256,6 +311,7 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
 {
     __shared__ __align__(16) bf16 sw[9 * C * PSTR];
     __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
+    __shared__ __align__(16) bf16 so[TROWS * TPX * PSTR];
     const int tid = threadIdx.x;
     stage_weights(wl, sw);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
@@ -275,7 +331,7 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
         __syncthreads();
         // the next tile's patch loads fly while this tile's matrix products run
         if (tile + (int)gridDim.x < ntiles) patch_load(in, tile + gridDim.x, tiles_w, tiles_h, H, W, reg);
-        conv32_tile<MIRROR>(sw, sp, tile, tiles_w, tiles_h, H, W, out, mask);
+        conv32_tile<MIRROR>(sw, sp, so, tile, tiles_w, tiles_h, H, W, out, mask);
     }
 }
 
@@ -296,6 +352,7 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
     __shared__ __align__(16) bf16 sw[9 * C * PSTR];
     __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
     __shared__ float sx[XROWS * XCOLS];
+    __shared__ __align__(16) bf16 so[TROWS * TPX * PSTR];
     const int tid = threadIdx.x;
     stage_weights(wl, sw);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
@@ -329,7 +386,7 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
             for (int k = 0; k < 4; ++k) dst[k] = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]);
         }
         __syncthreads();
-        conv32_tile<false>(sw, sp, tile, tiles_w, tiles_h, H, W, out, nullptr);
+        conv32_tile<false>(sw, sp, so, tile, tiles_w, tiles_h, H, W, out, nullptr);
     }
 }
 
