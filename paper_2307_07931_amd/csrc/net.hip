@@ -357,17 +357,35 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
     stage_weights(wl, sw);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
     const int ntiles = B * tiles_h * tiles_w;
+    // x of a tile's neighbourhood, XPER values per thread, loaded one tile ahead (in flight
+    // during the current tile's layer 1 and matrix products); `inside` says which of them
+    // lie in the image (the others stand for the zero padding)
+    constexpr int XPER = (XROWS * XCOLS + BX - 1) / BX;
+    TX xr[XPER];
+    bool inside[XPER];
+    auto xload = [&](int t) {
+        const int tw = t % tiles_w, th = (t / tiles_w) % tiles_h, b = t / (tiles_w * tiles_h);
+        const int i0 = th * TROWS, j0 = tw * TPX;
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int q = tid + u * BX;
+            const int ii = i0 - 2 + q / XCOLS, jj = j0 - 2 + q % XCOLS;
+            inside[u] = q < XROWS * XCOLS && ii >= 0 && ii < H && jj >= 0 && jj < W;
+            xr[u] = inside[u] ? x[((long long)b * H + ii) * ldx + jj] : (TX)0;
+        }
+    };
+    if ((int)blockIdx.x < ntiles) xload(blockIdx.x);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
+        const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h;
         const int i0 = th * TROWS, j0 = tw * TPX;
         __syncthreads();  // the previous tile's reads of sx and sp are done
-        for (int q = tid; q < XROWS * XCOLS; q += BX) {
-            const int ii = i0 - 2 + q / XCOLS, jj = j0 - 2 + q % XCOLS;
-            float v = 0.0f;
-            if (ii >= 0 && ii < H && jj >= 0 && jj < W) v = l1_input(x[((long long)b * H + ii) * ldx + jj], scale);
-            sx[q] = v;
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int q = tid + u * BX;
+            if (q < XROWS * XCOLS) sx[q] = inside[u] ? l1_input(xr[u], scale) : 0.0f;
         }
         __syncthreads();
+        if (tile + (int)gridDim.x < ntiles) xload(tile + gridDim.x);
         for (int q = tid; q < PROWS * PCOLS; q += BX) {
             const int pr = q / PCOLS, pc = q % PCOLS;
             const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
