@@ -59,8 +59,8 @@ struct NetW {
     bf16 *w2b;  // [t][ci][co]  (input gradient: rows = input channel, k = output channel)
     bf16 *w3f, *w3b;
     bf16 *w4;   // [ci][t]
-    float *w1s, *w4s;  // the BF16 values of w1 and w4 as FP32, read by the thin layers with
-                       // wave-uniform addresses (scalar loads, so the weights sit in SGPRs)
+    float *w1s;  // the BF16 values of w1 as FP32, read by layer 1 with wave-uniform
+                 // addresses (scalar loads, so the weights sit in SGPRs)
 };
 
 __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restrict__ w, NetW nw)
@@ -79,7 +79,6 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
         (l3 ? nw.w3b : nw.w2b)[(t * C + ci) * C + co] = b;
     } else {
         nw.w4[q - OFF4] = b;  // (1, ci, a, c) -> ci*9 + t
-        nw.w4s[q - OFF4] = bf16_to_f32(b.bits);
     }
 }
 
@@ -408,21 +407,33 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
     }
 }
 
-// Layer 4: 32 channels -> 1, output FP32 into rows of ldy.  Tiles of 4 rows x 64 pixels (the
-// convolution's), one pixel per thread; the a3 patch (6 x 66 pixels, rows padded to PSTR
-// elements) and the weights are staged in LDS, and each thread reads its 9 neighbours' 32
-// channels as 16-byte LDS loads.  Blocks loop over tiles with the next tile's patch loads
-// in flight while the current tile is summed, as the convolution does.
-__global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const float *__restrict__ w4s,
+// Layer 4: 32 channels -> 1, output FP32 into rows of ldy, on the matrix cores.  With
+// z_t(q) = sum over the 32 input channels of w4[ci][t] a3(q, ci), the output is
+// y(p) = z_0(p + o_0) + ... + z_8(p + o_8) (o_t the tap offsets, taps in order).  Tiles of
+// 4 rows x 64 pixels (the convolution's): the block stages the a3 patch (6 x 66 pixels,
+// rows padded to PSTR elements), forms z for all nine taps at every patch pixel as
+// v_mfma_f32_16x16x32_bf16 products (rows: taps, 9 of 16 used; columns: 16 patch pixels;
+// k: the 32 channels) into LDS, and each thread then adds its pixel's nine z values.
+// Blocks loop over tiles with the next tile's patch loads in flight, as the convolution
+// does.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int L4_NPIX = PROWS * PCOLS;         // patch pixels
+constexpr int L4_GROUPS = (L4_NPIX + 15) / 16;  // 16-pixel column groups of the products
+__global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const bf16 *__restrict__ w4,
                                                     float *__restrict__ y, int ldy, int B, int H, int W)
 {
-#pragma clang fp contract(fast)
     static_assert(LT_ROWS == TROWS && LT_PX == TPX, "layer 4 uses the convolution's tiles and patches");
-    // weights tap-major in LDS: the 8 channels of one 16-byte activation read take their
-    // 8 weights with two 16-byte reads (the same address in every lane)
-    __shared__ __align__(16) float sw[9 * C];
-    __shared__ __align__(16) bf16 sp[PROWS * PCOLS * PSTR];
-    for (int q = threadIdx.x; q < NW4; q += BX) sw[(q % 9) * C + q / 9] = w4s[q];
+    __shared__ __align__(16) bf16 sp[L4_NPIX * PSTR];
+    __shared__ float sz[9][L4_GROUPS * 16];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;  // product column (pixel of the group); k and row quarter
+    // A: row = tap col (taps 9..15 zero), k = channels 8 kq .. 8 kq + 7
+    bf16x8 aw;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const bf16 wt = col < 9 ? w4[(8 * kq + e) * 9 + col] : bf16{0};
+        aw[e] = __builtin_bit_cast(__bf16, wt.bits);
+    }
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
     const int ntiles = B * tiles_h * tiles_w;
     const int r = threadIdx.x / TPX, c = threadIdx.x % TPX;
@@ -430,7 +441,7 @@ __global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3,
     if ((int)blockIdx.x < ntiles) patch_load(a3, blockIdx.x, tiles_w, tiles_h, H, W, reg);
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int tw = tile % tiles_w, th = (tile / tiles_w) % tiles_h, b = tile / (tiles_w * tiles_h);
-        __syncthreads();  // the previous tile's LDS reads are done (first pass: weights stored)
+        __syncthreads();  // the previous tile's reads of sp and sz are done
 #pragma unroll
         for (int u = 0; u < PPER; ++u) {
             const int q = (int)threadIdx.x + u * BX;
@@ -441,26 +452,23 @@ __global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3,
         }
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) patch_load(a3, tile + gridDim.x, tiles_w, tiles_h, H, W, reg);
+        for (int g = wv; g < L4_GROUPS; g += BX / 64) {
+            const int px = g * 16 + col;
+            const int pxr = px < L4_NPIX ? px : 0;  // columns past the patch read pixel 0, unused
+            bf16x8 bv;
+            __builtin_memcpy(&bv, sp + pxr * PSTR + 8 * kq, 16);
+            const f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bv, f32x4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+            // lane holds rows (taps) 4 kq + e of column col
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (4 * kq + e < 9) sz[4 * kq + e][px] = d[e];
+        }
+        __syncthreads();
         const int i = th * TROWS + r, j = tw * TPX + c;
         if (i >= H || j >= W) continue;
         float acc = 0.0f;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const bf16 *px = sp + ((r + 1 + tap_dy(t, false)) * PCOLS + (c + 1 + tap_dx(t, false))) * PSTR;
-#pragma unroll
-            for (int c8 = 0; c8 < 4; ++c8) {
-                const uint4 u = *reinterpret_cast<const uint4 *>(px + c8 * 8);
-                const float4 wa = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8);
-                const float4 wb = *reinterpret_cast<const float4 *>(sw + t * C + c8 * 8 + 4);
-                const float wv[8] = {wa.x, wa.y, wa.z, wa.w, wb.x, wb.y, wb.z, wb.w};
-                const unsigned wd[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    acc += wv[2 * e] * __uint_as_float(wd[e] << 16);
-                    acc += wv[2 * e + 1] * __uint_as_float(wd[e] & 0xffff0000u);
-                }
-            }
-        }
+        for (int t = 0; t < 9; ++t) acc += sz[t][(r + 1 + tap_dy(t, false)) * PCOLS + (c + 1 + tap_dx(t, false))];
         y[((long long)b * H + i) * ldy + j] = acc;
     }
 }
@@ -994,9 +1002,8 @@ hipError_t net_alloc(NetState &s)
     s.nw.w3f = s.nw.w2b + NW2;
     s.nw.w3b = s.nw.w3f + NW2;
     s.nw.w4 = s.nw.w3b + NW2;
-    if ((e = hipMalloc(&s.ws, sizeof(float) * (NW1 + NW4))) != hipSuccess) return e;
+    if ((e = hipMalloc(&s.ws, sizeof(float) * NW1)) != hipSuccess) return e;
     s.nw.w1s = s.ws;
-    s.nw.w4s = s.ws + NW1;
     static_assert((size_t)WT_WAVES * NW1 <= (size_t)WGM_BLOCKS * NW2, "thin partials fit the partial buffer");
     if ((e = hipMalloc(&s.mid, sizeof(float) * (size_t)RS * NW2)) != hipSuccess) return e;
     return hipMalloc(&s.part, sizeof(float) * (size_t)WGM_BLOCKS * NW2);
@@ -1060,7 +1067,7 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
                        (const bf16 *)nullptr, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3,
                        (const bf16 *)nullptr, B, H, W);
-    hipLaunchKernelGGL(l4_fwd_kernel, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
     s.last_pixels = N;
     return hipGetLastError();
 }
@@ -1082,7 +1089,7 @@ hipError_t net_infer_forward(NetState &s, int xdt, const void *x, int ldx, doubl
                            s.nw.w2f, s.a2, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(cb), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3, (const bf16 *)nullptr,
                        B, H, W);
-    hipLaunchKernelGGL(l4_fwd_kernel, dim3(cb), dim3(BX), 0, st, s.a3, s.nw.w4s, y, ldy, B, H, W);
+    hipLaunchKernelGGL(l4_fwd_kernel, dim3(cb), dim3(BX), 0, st, s.a3, s.nw.w4, y, ldy, B, H, W);
     s.last_pixels = 0;  // the layer-1 activations of this pass were never stored
     return hipGetLastError();
 }
