@@ -59,8 +59,6 @@ struct NetW {
     bf16 *w2b;  // [t][ci][co]  (input gradient: rows = input channel, k = output channel)
     bf16 *w3f, *w3b;
     bf16 *w4;   // [ci][t]
-    float *w1s;  // the BF16 values of w1 as FP32, read by layer 1 with wave-uniform
-                 // addresses (scalar loads, so the weights sit in SGPRs)
 };
 
 __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restrict__ w, NetW nw)
@@ -70,7 +68,6 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
     const bf16 b = tobf(w[q]);
     if (q < OFF2) {
         nw.w1[q] = b;  // (co, 1, a, c) -> co*9 + t
-        nw.w1s[q] = bf16_to_f32(b.bits);
     } else if (q < OFF4) {
         const bool l3 = q >= OFF3;
         const int r = q - (l3 ? OFF3 : OFF2);
@@ -87,21 +84,47 @@ __global__ __launch_bounds__(BX) void prep_weights_kernel(const float *__restric
 constexpr int LT_ROWS = 4, LT_PX = 64;
 static_assert(LT_ROWS * LT_PX == BX, "one pixel per thread");
 
-// Layer 1 of one pixel from its 3 x 3 input neighbourhood xv (tap order, BF16 values held
-// as FP32): 32 channels, each an FP32 fused multiply-add chain over the 9 taps, ReLU,
-// rounded to BF16 and packed in pairs.  l1_fwd_kernel and the fused first convolution
-// both call it, so both produce the same bits.
-__device__ __forceinline__ void l1_pixel(const float (&xv)[9], const float *__restrict__ sw, unsigned (&pk)[C / 2])
+// Layer 1 on the matrix cores, 32 pixels per v_mfma_f32_32x32x16_bf16: rows = the 32
+// output channels, columns = the pixels, k = the 9 taps (then 7 zeros).  l1_weights gives
+// a lane's part of the weight operand (row lane mod 32, taps 8 (lane / 32) + 0..7);
+// l1_group takes the lane's eight inputs of its pixel (column lane mod 32) at those taps
+// and returns the products (the lane's channels 8g + 4 (lane / 32) + e in element 4g + e).
+// The layer-1 kernel and the fused first convolution both use them, so both produce the
+// same bits.
+__device__ __forceinline__ bf16x8 l1_weights(const bf16 *__restrict__ w1)
 {
+    const int lane = threadIdx.x & 63, co = lane & 31, kg = lane >> 5;
+    bf16x8 a;
 #pragma unroll
-    for (int co = 0; co < C; co += 2) {
-        float acc0 = 0.0f, acc1 = 0.0f;
+    for (int e = 0; e < 8; ++e) {
+        const int t = 8 * kg + e;
+        a[e] = __builtin_bit_cast(__bf16, t < 9 ? w1[co * 9 + t].bits : (uint16_t)0);
+    }
+    return a;
+}
+
+__device__ __forceinline__ f32x16 l1_group(const bf16x8 &aw, const float (&xt)[8])
+{
+    bf16x8 b;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            acc0 = __builtin_fmaf(sw[co * 9 + t], xv[t], acc0);
-            acc1 = __builtin_fmaf(sw[(co + 1) * 9 + t], xv[t], acc1);
-        }
-        pk[co / 2] = (unsigned)f32_to_bf16_rne(relu(acc0)) | ((unsigned)f32_to_bf16_rne(relu(acc1)) << 16);
+    for (int e = 0; e < 8; ++e) b[e] = __builtin_bit_cast(__bf16, (uint16_t)(__float_as_uint(xt[e]) >> 16));
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, b, f32x16{}, 0, 0, 0);
+}
+
+// The lane's 16 channels of its pixel after ReLU, rounded to BF16, at dst (a pixel's
+// channel row), as four 8-byte stores.
+__device__ __forceinline__ void l1_store(const f32x16 &acc, bool zero, bf16 *dst)
+{
+    const int kg = (threadIdx.x & 63) >> 5;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        unsigned short v[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = zero ? (unsigned short)0 : f32_to_bf16_rne(relu(acc[4 * g + e]));
+        uint2 pk;
+        pk.x = (unsigned)v[0] | ((unsigned)v[1] << 16);
+        pk.y = (unsigned)v[2] | ((unsigned)v[3] << 16);
+        *reinterpret_cast<uint2 *>(dst + 8 * g + 4 * kg) = pk;
     }
 }
 
@@ -112,42 +135,44 @@ template <typename TX> __device__ __forceinline__ float l1_input(TX v, double sc
 }
 
 // Layer 1: x (rows of ldx, FP64 or FP32) times `scale`, rounded to FP32 and then to
-// BF16, -> 32 channels, ReLU.  FP32 accumulation (fused multiply-add).
+// BF16, -> 32 channels, ReLU, on the matrix cores (l1_group).  One block per tile of
+// 4 rows x 64 pixels: the input patch (1-pixel halo) is staged in LDS, each wave forms two
+// 32-pixel groups, and the results go through LDS so that every store instruction of a
+// wave writes 1 KB of consecutive memory (16 pixels of one row).
 template <typename TX>
 __global__ __launch_bounds__(BX) void l1_fwd_kernel(const TX *__restrict__ x, int ldx, double scale,
-                                                    const float *__restrict__ sw, bf16 *__restrict__ a1, int B,
+                                                    const bf16 *__restrict__ w1, bf16 *__restrict__ a1, int B,
                                                     int H, int W)
 {
-#pragma clang fp contract(fast)
-    __shared__ float sx[(LT_ROWS + 2) * (LT_PX + 2)];
+    constexpr int SXC = LT_PX + 2;
+    constexpr int OSTR = 40;  // pixel slots of the output staging, padded to 80 bytes
+    __shared__ float sx[(LT_ROWS + 2) * SXC];
+    __shared__ __align__(16) bf16 so[LT_ROWS * LT_PX * OSTR];
     const int tiles_w = (W + LT_PX - 1) / LT_PX, tiles_h = (H + LT_ROWS - 1) / LT_ROWS;
     const int tw = (int)(blockIdx.x % tiles_w), th = (int)((blockIdx.x / tiles_w) % tiles_h);
     const int b = (int)(blockIdx.x / ((unsigned)tiles_w * tiles_h));
     const int i0 = th * LT_ROWS, j0 = tw * LT_PX;
-    for (int q = threadIdx.x; q < (LT_ROWS + 2) * (LT_PX + 2); q += BX) {
-        const int pr = q / (LT_PX + 2), pc = q % (LT_PX + 2);
+    const bf16x8 aw = l1_weights(w1);
+    for (int q = threadIdx.x; q < (LT_ROWS + 2) * SXC; q += BX) {
+        const int pr = q / SXC, pc = q % SXC;
         const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
         float v = 0.0f;
         if (ii >= 0 && ii < H && jj >= 0 && jj < W) v = l1_input(x[((long long)b * H + ii) * ldx + jj], scale);
         sx[q] = v;
     }
     __syncthreads();
-    const int r = threadIdx.x / LT_PX, c = threadIdx.x % LT_PX;
-    const int i = i0 + r, j = j0 + c;
-    // each thread's 64-byte pixel goes through LDS so that every store instruction of a
-    // wave writes 1 KB of consecutive memory (16 pixels of one row) instead of 16 bytes
-    // from each of 64 pixels 64 bytes apart; pixel slots are padded to 80 bytes
-    constexpr int OSTR = 40;
-    __shared__ __align__(16) bf16 so[LT_ROWS * LT_PX * OSTR];
-    if (i < H && j < W) {
-        float xv[9];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, kg = lane >> 5;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) xv[t] = sx[(r + 1 + tap_dy(t, false)) * (LT_PX + 2) + (c + 1 + tap_dx(t, false))];
-        unsigned pk[C / 2];
-        l1_pixel(xv, sw, pk);
-        uint4 *st = reinterpret_cast<uint4 *>(so + threadIdx.x * OSTR);
+    for (int h = 0; h < 2; ++h) {
+        const int px = (2 * wv + h) * 32 + (lane & 31);  // pixel of the tile, row-major
+        const int r = px / LT_PX, c = px % LT_PX;
+        float xt[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) st[q] = make_uint4(pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]);
+        for (int e = 0; e < 8; ++e) {
+            const int t = 8 * kg + e;
+            xt[e] = t < 9 ? sx[(r + 1 + tap_dy(t, false)) * SXC + (c + 1 + tap_dx(t, false))] : 0.0f;
+        }
+        l1_store(l1_group(aw, xt), false, so + px * OSTR);
     }
     __syncthreads();
 #pragma unroll
@@ -337,15 +362,16 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
 // Layers 1 and 2 in one pass (inference: the layer-1 activations are not kept).  Per tile
 // the block stages the input x of the patch's neighbourhood ((PROWS + 2) x (PCOLS + 2)
 // pixels, rounded as the first layer's input), computes layer 1 for the PROWS x PCOLS
-// patch pixels with l1_pixel straight into the patch buffer (zero outside the image, the
+// patch pixels with l1_group straight into the patch buffer (zero outside the image, the
 // second layer's zero padding), then runs the second layer's matrix products as
 // conv32_kernel does.  The patch holds exactly the values l1_fwd_kernel would have
 // stored, so the output equals l1_fwd_kernel followed by conv32_kernel bit for bit, with
 // the 64-byte-per-pixel layer-1 activations never written to or read from memory.
 constexpr int XROWS = PROWS + 2, XCOLS = PCOLS + 2;
+constexpr int L1_GROUPS = (PROWS * PCOLS + 31) / 32;  // 32-pixel groups of layer 1 per patch
 template <typename TX>
 __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, int ldx, double scale,
-                                                    const float *__restrict__ w1s, const bf16 *__restrict__ wl,
+                                                    const bf16 *__restrict__ w1, const bf16 *__restrict__ wl,
                                                     bf16 *__restrict__ out, int B, int H, int W)
 {
     __shared__ __align__(16) bf16 sw[9 * C * PSTR];
@@ -354,6 +380,7 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
     __shared__ __align__(16) bf16 so[TROWS * TPX * PSTR];
     const int tid = threadIdx.x;
     stage_weights(wl, sw);
+    const bf16x8 aw = l1_weights(w1);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
     const int ntiles = B * tiles_h * tiles_w;
     // x of a tile's neighbourhood, XPER values per thread, loaded one tile ahead (in flight
@@ -385,22 +412,22 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
         }
         __syncthreads();
         if (tile + (int)gridDim.x < ntiles) xload(tile + gridDim.x);
-        for (int q = tid; q < PROWS * PCOLS; q += BX) {
-            const int pr = q / PCOLS, pc = q % PCOLS;
+        // layer 1 for the patch pixels, 32 per group; pixels outside the image are the
+        // second layer's zero padding
+        for (int g = tid >> 6; g < L1_GROUPS; g += BX / 64) {
+            const int px = g * 32 + (tid & 31);
+            const bool valid = px < PROWS * PCOLS;
+            const int pxc = valid ? px : 0;  // columns past the patch compute pixel 0, unused
+            const int pr = pxc / PCOLS, pc = pxc % PCOLS;
             const int ii = i0 - 1 + pr, jj = j0 - 1 + pc;
-            unsigned pk[C / 2];
-            if (ii >= 0 && ii < H && jj >= 0 && jj < W) {
-                float xv[9];
+            float xt[8];
 #pragma unroll
-                for (int t = 0; t < 9; ++t) xv[t] = sx[(pr + 1 + tap_dy(t, false)) * XCOLS + (pc + 1 + tap_dx(t, false))];
-                l1_pixel(xv, w1s, pk);
-            } else {
-#pragma unroll
-                for (int k = 0; k < C / 2; ++k) pk[k] = 0u;
+            for (int e = 0; e < 8; ++e) {
+                const int t = 8 * ((tid & 63) >> 5) + e;
+                xt[e] = t < 9 ? sx[(pr + 1 + tap_dy(t, false)) * XCOLS + (pc + 1 + tap_dx(t, false))] : 0.0f;
             }
-            uint4 *dst = reinterpret_cast<uint4 *>(sp + q * PSTR);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) dst[k] = make_uint4(pk[4 * k], pk[4 * k + 1], pk[4 * k + 2], pk[4 * k + 3]);
+            const f32x16 acc = l1_group(aw, xt);
+            if (valid) l1_store(acc, !(ii >= 0 && ii < H && jj >= 0 && jj < W), sp + px * PSTR);
         }
         __syncthreads();
         conv32_tile<false>(sw, sp, so, tile, tiles_w, tiles_h, H, W, out, nullptr);
@@ -960,7 +987,7 @@ struct NetState {
     NetW nw{};
     long long pixels = 0;  // workspace capacity
     bf16 *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *dz1 = nullptr, *dz2 = nullptr, *dz3 = nullptr;
-    float *y = nullptr, *dy = nullptr, *part = nullptr, *mid = nullptr, *ws = nullptr;
+    float *y = nullptr, *dy = nullptr, *part = nullptr, *mid = nullptr;
     double *dpart = nullptr;
     long long step = 0;
     long long last_pixels = 0;  // pixels of the last forward pass (0: none yet)
@@ -982,7 +1009,7 @@ struct NetState {
     ~NetState()
     {
         free_workspace();
-        for (float **p : {&w, &m, &v, &g, &part, &mid, &ws}) {
+        for (float **p : {&w, &m, &v, &g, &part, &mid}) {
             if (*p) (void)hipFree(*p);
             *p = nullptr;
         }
@@ -1002,8 +1029,6 @@ hipError_t net_alloc(NetState &s)
     s.nw.w3f = s.nw.w2b + NW2;
     s.nw.w3b = s.nw.w3f + NW2;
     s.nw.w4 = s.nw.w3b + NW2;
-    if ((e = hipMalloc(&s.ws, sizeof(float) * NW1)) != hipSuccess) return e;
-    s.nw.w1s = s.ws;
     static_assert((size_t)WT_WAVES * NW1 <= (size_t)WGM_BLOCKS * NW2, "thin partials fit the partial buffer");
     if ((e = hipMalloc(&s.mid, sizeof(float) * (size_t)RS * NW2)) != hipSuccess) return e;
     return hipMalloc(&s.part, sizeof(float) * (size_t)WGM_BLOCKS * NW2);
@@ -1058,10 +1083,10 @@ hipError_t net_forward(NetState &s, int xdt, const void *x, int ldx, double scal
     if (e != hipSuccess) return e;
     const unsigned lt = thin_blocks(B, H, W);
     if (xdt == F64)
-        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(lt), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1s,
+        hipLaunchKernelGGL(l1_fwd_kernel<double>, dim3(lt), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1,
                            s.a1, B, H, W);
     else
-        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(lt), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1s,
+        hipLaunchKernelGGL(l1_fwd_kernel<float>, dim3(lt), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1,
                            s.a1, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(conv_blocks(B, H, W)), dim3(BX), 0, st, s.a1, s.nw.w2f, s.a2,
                        (const bf16 *)nullptr, B, H, W);
@@ -1082,10 +1107,10 @@ hipError_t net_infer_forward(NetState &s, int xdt, const void *x, int ldx, doubl
     if (e != hipSuccess) return e;
     const unsigned cb = conv_blocks(B, H, W);
     if (xdt == F64)
-        hipLaunchKernelGGL(conv12_kernel<double>, dim3(cb), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1s,
+        hipLaunchKernelGGL(conv12_kernel<double>, dim3(cb), dim3(BX), 0, st, (const double *)x, ldx, scale, s.nw.w1,
                            s.nw.w2f, s.a2, B, H, W);
     else
-        hipLaunchKernelGGL(conv12_kernel<float>, dim3(cb), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1s,
+        hipLaunchKernelGGL(conv12_kernel<float>, dim3(cb), dim3(BX), 0, st, (const float *)x, ldx, scale, s.nw.w1,
                            s.nw.w2f, s.a2, B, H, W);
     hipLaunchKernelGGL(conv32_kernel<false>, dim3(cb), dim3(BX), 0, st, s.a2, s.nw.w3f, s.a3, (const bf16 *)nullptr,
                        B, H, W);
