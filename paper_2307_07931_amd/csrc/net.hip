@@ -446,12 +446,15 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int L4_NPIX = PROWS * PCOLS;         // patch pixels
 constexpr int L4_GROUPS = (L4_NPIX + 15) / 16;  // 16-pixel column groups of the products
+// row pitch of the per-tap sums in LDS: 4 mod 16 words, so the four taps a product writes
+// at once (rows 4 kq + e, 16 pixels each) start in different banks
+constexpr int L4_ZSTR = L4_GROUPS * 16 + 4;
 __global__ __launch_bounds__(BX) void l4_fwd_kernel(const bf16 *__restrict__ a3, const bf16 *__restrict__ w4,
                                                     float *__restrict__ y, int ldy, int B, int H, int W)
 {
     static_assert(LT_ROWS == TROWS && LT_PX == TPX, "layer 4 uses the convolution's tiles and patches");
     __shared__ __align__(16) bf16 sp[L4_NPIX * PSTR];
-    __shared__ float sz[9][L4_GROUPS * 16];
+    __shared__ float sz[9][L4_ZSTR];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;  // product column (pixel of the group); k and row quarter
     // A: row = tap col (taps 9..15 zero), k = channels 8 kq .. 8 kq + 7
