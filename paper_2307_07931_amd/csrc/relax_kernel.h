@@ -690,7 +690,8 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 // delivers each row differs.  Bands alternate direction, so two neighbouring bands read the
 // 2K rows they share at the same end of their lives (both first or both last) while they
 // run side by side, and the second read of a shared row tends to hit the L2.
-template <typename T, int V, int K, bool VEC, bool FILLING, bool UP, bool EDGE>
+template <typename T, int V, int K, bool VEC, bool FILLING, bool UP, bool EDGE, int COLS = 0,
+          bool ROWFIX = false>
 __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, int s0, int base,
                                               typename Elem<T>::A (&win)[K][3][V],
                                               typename Elem<T>::A (&lf)[K + 1][V],
@@ -710,18 +711,43 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
     const A w = (A)p.w, lam = (A)p.lam;
     const int fc = VEC ? mc : mc - 1;
-    // edge tiles (homogeneous Dirichlet): which of this lane's columns are 1 and n
-    bool west[V], east[V];
+    // Edge tiles (homogeneous Dirichlet) keep the ghost cells of every time level equal to
+    // the odd reflection of their neighbours inside, as a refresh of the ghost layer
+    // before each sweep would: after each level's row is formed, column 0 := -column 1 and
+    // column n + 1 := -column n in the waves that hold them (COLS: 1 column 0, 2 column
+    // n + 1 in the lane of column n, 3 both or column n + 1 starting a lane; column 0 is
+    // element 0 of a lane since waves start on multiples of V), and the ghost rows 0 and
+    // n + 1 := -rows 1 and n, whichever of each pair comes second in the stream being set
+    // when it does (ROWFIX).  Every interior cell then reads the value the substitution
+    // N = -C (or S, W, E) gives, with the interior arithmetic.  The column rule is one
+    // select per level in the waves at the left or right edge, and the row rule runs only
+    // while the pipeline fills (bands that reach a ghost row stream away from it), so the
+    // code of the other blocks stays as straight as the interior tiles'.
+    auto ghost_cols = [&](A(&a)[V]) {
+        if constexpr (COLS == 1 || COLS == 3) a[0] = (mc == 0) ? -a[1] : a[0];
+        if constexpr (COLS >= 2) {
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        west[v] = EDGE && mc + v == 1;
-        east[v] = EDGE && mc + v == n;
-    }
+            for (int v = 1; v < V; ++v) a[v] = (mc + v == n + 1) ? -a[v - 1] : a[v];
+        }
+        if constexpr (COLS == 3) {
+            const A pl = lane_from_left(a[V - 1]);
+            a[0] = (mc == n + 1) ? -pl : a[0];
+        }
+    };
 #pragma unroll
     for (int q = 0; q < U; ++q) {
         const int s = s0 + q;       // step
         const int x = base + D * s;  // phi row arriving at this step
         IO::unpack(pf[q % PR], win[0][q % 3]);
+        if constexpr (EDGE && COLS != 0) ghost_cols(win[0][q % 3]);  // the same rules for the input rows
+        if constexpr (EDGE && ROWFIX) {  // selects, not branches: the code stays straight
+            const int pq = (q + 2) % 3;  // slot of the previous step's row
+            const bool second = x == (UP ? 0 : n + 1), first = x == (UP ? n : 1);
+#pragma unroll
+            for (int v = 0; v < V; ++v) win[0][q % 3][v] = second ? -win[0][pq][v] : win[0][q % 3][v];
+#pragma unroll
+            for (int v = 0; v < V; ++v) win[0][pq][v] = first ? -win[0][q % 3][v] : win[0][pq][v];
+        }
         {
             A fo[V], fv[V];
             IO::unpack(pff[q % PR], fo);
@@ -754,47 +780,49 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
 #pragma unroll
             for (int v = 0; v < V; ++v) {
                 const A C = win[t - 1][sc][v];
-                A N = win[t - 1][sn][v];
-                A S = win[t - 1][ss][v];
-                A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
-                A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
-                if constexpr (EDGE) {
-                    // odd reflection across the boundary faces; the values computed in
-                    // ghost and outside cells are never read by an interior cell
-                    N = (r == 1) ? -C : N;
-                    S = (r == n) ? -C : S;
-                    Wn = west[v] ? -C : Wn;
-                    En = east[v] ? -C : En;
-                }
+                const A N = win[t - 1][sn][v];
+                const A S = win[t - 1][ss][v];
+                const A Wn = (v == 0) ? left : win[t - 1][sc][v - 1];
+                const A En = (v == V - 1) ? right : win[t - 1][sc][v + 1];
                 const A st = ((sub4(N, C) + Wn) + En) + S;
                 nv[v] = E::round((C + w * st) - lf[sf][v]);
             }
+            if constexpr (EDGE && COLS != 0) ghost_cols(nv);
             if (t < K) {
+                if constexpr (EDGE && ROWFIX) {
+                    // the second ghost row of its pair takes the mirror of the row before it;
+                    // the first is set once the row after it (its mirror) is formed
+                    const bool second = r == (UP ? 0 : n + 1), first = r == (UP ? n : 1);
+#pragma unroll
+                    for (int v = 0; v < V; ++v) nv[v] = second ? -win[t][so][v] : nv[v];
+#pragma unroll
+                    for (int v = 0; v < V; ++v) win[t][so][v] = first ? -nv[v] : win[t][so][v];
+                }
 #pragma unroll
                 for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
             } else if (UP ? r >= y0 : r < y1) {  // the other bound holds once level K runs
                 if constexpr (!EDGE) {
                     store_cols<T, V, VEC>(stream_rsrc(sout, n + 2, rb), mc, oc0, oc1, true, nv, false,
                                           p.nt_store != 0);
+                } else if constexpr (!ROWFIX) {
+                    // rows 2 .. n - 1 only: the row with its ghost columns
+                    const int hi = min(oc1, n + 2);
+                    store_cols<T, V, VEC>(stream_rsrc(sout, n + 2, rb), mc, oc0, hi, oc0 % V == 0 && hi % V == 0,
+                                          nv, false, p.nt_store != 0);
                 } else if (r >= 1 && r <= n) {
-                    // interior columns of the row, the ghosts of columns 1 and n, and the
-                    // ghost rows 0 and n + 1 as the mirrors of rows 1 and n
-                    const int rc0 = max(oc0, 1), rc1 = min(oc1, n + 1);
-                    const auto ro = row_rsrc(p.out, r, n + 2, rb);
-                    store_cols<T, V, VEC>(ro, mc, rc0, rc1, tl.whole, nv, false);
-                    if (!tl.whole) {
-#pragma unroll
-                        for (int v = 0; v < V; ++v) {
-                            const bool mine = mc + v >= rc0 && mc + v < rc1;
-                            Store1<T>::st(ro, 0, mine && west[v], -nv[v]);
-                            Store1<T>::st(ro, n + 1, mine && east[v], -nv[v]);
-                        }
-                    }
+                    // the row with its ghost columns (which hold the mirrors of columns 1
+                    // and n), and the ghost rows 0 and n + 1 as the mirrors of rows 1 and n
+                    // (the four corners are left untouched)
+                    const int rc0 = max(oc0, 1), rc1 = min(oc1, n + 1), hi = min(oc1, n + 2);
+                    const bool nt = p.nt_store != 0;
+                    // whole vectors when both ends of the stored range fall on vector bounds
+                    store_cols<T, V, VEC>(stream_rsrc(sout, n + 2, rb), mc, oc0, hi, oc0 % V == 0 && hi % V == 0,
+                                          nv, false, nt);
                     if (r == 1)
-                        store_cols<T, V, VEC>(row_rsrc(p.out, 0, n + 2, rb), mc, rc0, rc1, tl.whole, nv, true);
+                        store_cols<T, V, VEC>(row_rsrc(p.out, 0, n + 2, rb), mc, rc0, rc1, tl.whole, nv, true, nt);
                     if (r == n)
-                        store_cols<T, V, VEC>(row_rsrc(p.out, n + 1, n + 2, rb), mc, rc0, rc1, tl.whole, nv,
-                                              true);
+                        store_cols<T, V, VEC>(row_rsrc(p.out, n + 1, n + 2, rb), mc, rc0, rc1, tl.whole, nv, true,
+                                              nt);
                 }
             }
         }
@@ -802,7 +830,7 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
     }
 }
 
-template <typename T, int V, int K, bool VEC, bool UP, bool EDGE>
+template <typename T, int V, int K, bool VEC, bool UP, bool EDGE, int COLS = 0>
 __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
 {
     using E = Elem<T>;
@@ -841,10 +869,22 @@ __device__ __forceinline__ void run_tile_renamed(const KArgs &p, const Tile &tl)
     RowStream sin = row_stream(p.in, base + D * PR, rb), sfr = row_stream(p.f, base + D * PR - 1, rbf),
               sout = row_stream(p.out, base - D * K, rb);
     int s0 = 0;
-    for (; s0 < steps && s0 < 2 * K; s0 += U)
-        renamed_block<T, V, K, VEC, true, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff, sin, sfr, sout);
-    for (; s0 < steps; s0 += U)
-        renamed_block<T, V, K, VEC, false, UP, EDGE>(p, tl, s0, base, win, lf, pf, pff, sin, sfr, sout);
+    if constexpr (!EDGE) {
+        for (; s0 < steps && s0 < 2 * K; s0 += U)
+            renamed_block<T, V, K, VEC, true, UP, false>(p, tl, s0, base, win, lf, pf, pff, sin, sfr, sout);
+        for (; s0 < steps; s0 += U)
+            renamed_block<T, V, K, VEC, false, UP, false>(p, tl, s0, base, win, lf, pf, pff, sin, sfr, sout);
+    } else {
+        // Bands that reach a ghost row stream away from it (relax_one_tile), so every row
+        // within K + 1 of it is formed in the first 2K + 2 steps: the two blocks that fill
+        // the pipeline, which alone apply the ghost-row rule.
+        for (; s0 < steps && s0 < 2 * K; s0 += U)
+            renamed_block<T, V, K, VEC, true, UP, true, COLS, true>(p, tl, s0, base, win, lf, pf, pff, sin, sfr,
+                                                                   sout);
+        for (; s0 < steps; s0 += U)
+            renamed_block<T, V, K, VEC, false, UP, true, COLS, false>(p, tl, s0, base, win, lf, pf, pff, sin, sfr,
+                                                                     sout);
+    }
 }
 
 // One wave tile of one problem: geometry, interior/edge dispatch, streaming loop.
@@ -875,11 +915,24 @@ __device__ __forceinline__ void relax_one_tile(const KArgs &p, int tile, int lan
                 run_tile_renamed<T, V, K, VEC, false, false>(p, tl);
             return;
         }
-        if (p.bc == DIRICHLET0) {
-            if (up)
-                run_tile_renamed<T, V, K, VEC, true, true>(p, tl);
-            else
-                run_tile_renamed<T, V, K, VEC, false, true>(p, tl);
+        // Dirichlet edge tiles: a band whose rows reach ghost row 0 streams down and one
+        // that reaches ghost row n + 1 streams up (so the ghost-row rule is needed only while
+        // the pipeline fills); a band reaching both takes the general path
+        const bool top = y0 - K <= 1, bot = y1 + K - 1 >= n;
+        if (p.bc == DIRICHLET0 && !(top && bot)) {
+            const bool up = bot || (!top && (ty & 1) != 0);
+            const bool hw = c0 <= 0, he = c0 + WAVE * V > n + 1;  // the wave holds column 0 / n + 1
+            const int cm = ((hw && he) || (he && (n + 1) % V == 0)) ? 3 : (hw ? 1 : (he ? 2 : 0));
+            switch (cm + (up ? 4 : 0)) {
+            case 0: run_tile_renamed<T, V, K, VEC, false, true, 0>(p, tl); break;
+            case 1: run_tile_renamed<T, V, K, VEC, false, true, 1>(p, tl); break;
+            case 2: run_tile_renamed<T, V, K, VEC, false, true, 2>(p, tl); break;
+            case 3: run_tile_renamed<T, V, K, VEC, false, true, 3>(p, tl); break;
+            case 4: run_tile_renamed<T, V, K, VEC, true, true, 0>(p, tl); break;
+            case 5: run_tile_renamed<T, V, K, VEC, true, true, 1>(p, tl); break;
+            case 6: run_tile_renamed<T, V, K, VEC, true, true, 2>(p, tl); break;
+            default: run_tile_renamed<T, V, K, VEC, true, true, 3>(p, tl); break;
+            }
             return;
         }
     }
