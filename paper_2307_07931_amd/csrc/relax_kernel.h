@@ -723,6 +723,7 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
     // select per level in the waves at the left or right edge, and the row rule runs only
     // while the pipeline fills (bands that reach a ghost row stream away from it), so the
     // code of the other blocks stays as straight as the interior tiles'.
+    const bool rowtile = y0 - K <= 1 || y1 + K - 1 >= n;  // the band reaches a ghost row
     auto ghost_cols = [&](A(&a)[V]) {
         if constexpr (COLS == 1 || COLS == 3) a[0] = (mc == 0) ? -a[1] : a[0];
         if constexpr (COLS >= 2) {
@@ -740,13 +741,15 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
         const int x = base + D * s;  // phi row arriving at this step
         IO::unpack(pf[q % PR], win[0][q % 3]);
         if constexpr (EDGE && COLS != 0) ghost_cols(win[0][q % 3]);  // the same rules for the input rows
-        if constexpr (EDGE && ROWFIX) {  // selects, not branches: the code stays straight
-            const int pq = (q + 2) % 3;  // slot of the previous step's row
-            const bool second = x == (UP ? 0 : n + 1), first = x == (UP ? n : 1);
+        if constexpr (EDGE && ROWFIX) {
+            if (rowtile) {  // side strips of the middle bands skip the row rule
+                const int pq = (q + 2) % 3;  // slot of the previous step's row
+                const bool second = x == (UP ? 0 : n + 1), first = x == (UP ? n : 1);
 #pragma unroll
-            for (int v = 0; v < V; ++v) win[0][q % 3][v] = second ? -win[0][pq][v] : win[0][q % 3][v];
+                for (int v = 0; v < V; ++v) win[0][q % 3][v] = second ? -win[0][pq][v] : win[0][q % 3][v];
 #pragma unroll
-            for (int v = 0; v < V; ++v) win[0][pq][v] = first ? -win[0][q % 3][v] : win[0][pq][v];
+                for (int v = 0; v < V; ++v) win[0][pq][v] = first ? -win[0][q % 3][v] : win[0][pq][v];
+            }
         }
         {
             A fo[V], fv[V];
@@ -790,13 +793,15 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
             if constexpr (EDGE && COLS != 0) ghost_cols(nv);
             if (t < K) {
                 if constexpr (EDGE && ROWFIX) {
-                    // the second ghost row of its pair takes the mirror of the row before it;
-                    // the first is set once the row after it (its mirror) is formed
-                    const bool second = r == (UP ? 0 : n + 1), first = r == (UP ? n : 1);
+                    if (rowtile) {
+                        // the second ghost row of its pair takes the mirror of the row before
+                        // it; the first is set once the row after it (its mirror) is formed
+                        const bool second = r == (UP ? 0 : n + 1), first = r == (UP ? n : 1);
 #pragma unroll
-                    for (int v = 0; v < V; ++v) nv[v] = second ? -win[t][so][v] : nv[v];
+                        for (int v = 0; v < V; ++v) nv[v] = second ? -win[t][so][v] : nv[v];
 #pragma unroll
-                    for (int v = 0; v < V; ++v) win[t][so][v] = first ? -nv[v] : win[t][so][v];
+                        for (int v = 0; v < V; ++v) win[t][so][v] = first ? -nv[v] : win[t][so][v];
+                    }
                 }
 #pragma unroll
                 for (int v = 0; v < V; ++v) win[t][sc][v] = nv[v];
