@@ -673,11 +673,11 @@ __device__ __forceinline__ void run_tile(const KArgs &p, const Tile &tl, unsigne
 }
 
 // Tiles of launches without norms whose K + 1 is a multiple of 3 (K = 2, 5, 8) -- interior
-// tiles, and with EDGE the edge tiles of homogeneous-Dirichlet grids, which substitute the
-// odd reflection for the neighbour across each boundary face and write the ghost layer:
-// the step loop is unrolled U = K + 1 times, so the 3-row windows of every level (3 | U),
-// the (K + 1)-row ring of lambda f (U rows) and a 3-deep ring of prefetched rows all rotate
-// by renaming: the row of step v of a level lives in slot v mod 3, lambda f of the phi row
+// tiles, and with EDGE the edge tiles of homogeneous-Dirichlet grids, which keep the ghost
+// cells of every level at the odd reflection (below) and write the ghost layer: the step
+// loop is unrolled U = K + 1 times, so the 3-row windows of every level (3 | U), the
+// (K + 1)-row ring of lambda f (U rows) and a 3-deep ring of prefetched rows all rotate by
+// renaming: the row of step v of a level lives in slot v mod 3, lambda f of the phi row
 // of step v in slot v mod U.  The product lambda f is formed once per row when the row
 // arrives and reused by all K levels: the same rounded product each level would form, so
 // the results are those of run_tile bit for bit.  Level t starts 2t steps after the first
