@@ -242,10 +242,24 @@ __device__ __forceinline__ void wave_lds_sync()
 // 16-byte stores of consecutive memory (1 KB per store instruction), where storing from
 // the accumulators directly scatters 8 bytes per lane over 32 pixels.  The backward's
 // ReLU mask comes in the same way, with coalesced loads.
+// A wave's weight operands for all 9 taps x 2 channel halves (72 registers), read from the
+// staged weights once per block and kept for every tile the block computes.
+struct ConvA {
+    bf16x8 a[9][2];
+};
+__device__ __forceinline__ void load_conv_weights(const bf16 *__restrict__ sw, ConvA &w)
+{
+    const int lane = threadIdx.x & 63, n = lane & 31, kg = lane >> 5;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int c16 = 0; c16 < 2; ++c16) __builtin_memcpy(&w.a[t][c16], sw + (t * C + n) * PSTR + c16 * 16 + kg * 8, 16);
+}
+
 template <bool MIRROR>
-__device__ __forceinline__ void conv32_tile(const bf16 *__restrict__ sw, const bf16 *__restrict__ sp,
-                                            bf16 *__restrict__ so, int tile, int tiles_w, int tiles_h, int H, int W,
-                                            bf16 *__restrict__ out, const bf16 *__restrict__ mask)
+__device__ __forceinline__ void conv32_tile(const ConvA &w, const bf16 *__restrict__ sp, bf16 *__restrict__ so,
+                                            int tile, int tiles_w, int tiles_h, int H, int W, bf16 *__restrict__ out,
+                                            const bf16 *__restrict__ mask)
 {
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int n = lane & 31, kg = lane >> 5;
@@ -258,12 +272,11 @@ __device__ __forceinline__ void conv32_tile(const bf16 *__restrict__ sw, const b
 #pragma unroll
         for (int c16 = 0; c16 < 2; ++c16) {
             const int k0 = c16 * 16 + kg * 8;
-            bf16x8 av, b0, b1;
-            __builtin_memcpy(&av, sw + (t * C + n) * PSTR + k0, 16);
+            bf16x8 b0, b1;
             __builtin_memcpy(&b0, sp + (pr * PCOLS + pc) * PSTR + k0, 16);
             __builtin_memcpy(&b1, sp + (pr * PCOLS + pc + 32) * PSTR + k0, 16);
-            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
-            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a[t][c16], b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(w.a[t][c16], b1, acc1, 0, 0, 0);
         }
     }
     const int i = i0 + wv;
@@ -338,6 +351,9 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
     __shared__ __align__(16) bf16 so[TROWS * TPX * PSTR];
     const int tid = threadIdx.x;
     stage_weights(wl, sw);
+    __syncthreads();
+    ConvA wr;
+    load_conv_weights(sw, wr);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
     const int ntiles = B * tiles_h * tiles_w;  // < 2^31: at most 2^31 pixels
     uint4 reg[PPER];
@@ -355,7 +371,7 @@ __global__ __launch_bounds__(BX) void conv32_kernel(const bf16 *__restrict__ in,
         __syncthreads();
         // the next tile's patch loads fly while this tile's matrix products run
         if (tile + (int)gridDim.x < ntiles) patch_load(in, tile + gridDim.x, tiles_w, tiles_h, H, W, reg);
-        conv32_tile<MIRROR>(sw, sp, so, tile, tiles_w, tiles_h, H, W, out, mask);
+        conv32_tile<MIRROR>(wr, sp, so, tile, tiles_w, tiles_h, H, W, out, mask);
     }
 }
 
@@ -380,6 +396,9 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
     __shared__ __align__(16) bf16 so[TROWS * TPX * PSTR];
     const int tid = threadIdx.x;
     stage_weights(wl, sw);
+    __syncthreads();
+    ConvA wr;
+    load_conv_weights(sw, wr);
     const bf16x8 aw = l1_weights(w1);
     const int tiles_w = (W + TPX - 1) / TPX, tiles_h = (H + TROWS - 1) / TROWS;
     const int ntiles = B * tiles_h * tiles_w;
@@ -430,7 +449,7 @@ __global__ __launch_bounds__(BX) void conv12_kernel(const TX *__restrict__ x, in
             if (valid) l1_store(acc, !(ii >= 0 && ii < H && jj >= 0 && jj < W), sp + px * PSTR);
         }
         __syncthreads();
-        conv32_tile<false>(sw, sp, so, tile, tiles_w, tiles_h, H, W, out, nullptr);
+        conv32_tile<false>(wr, sp, so, tile, tiles_w, tiles_h, H, W, out, nullptr);
     }
 }
 
