@@ -290,7 +290,6 @@ int px_relax_boxes(const px_problem *boxes, int nbx, int nby, int dtype, int nsw
                    px_ctx *ctx, void *stream);
 
 /*
- * Autotuner for batches: the tile rows of each problem size/*
  * Autotuner for batches: the tile rows of each problem size (the problems of that size
  * relaxed alone with the persistent kernel, 8 sweeps per launch, every candidate height),
  * then the sweeps per launch k in 1..8 for the whole batch.  Remembered in ctx for
