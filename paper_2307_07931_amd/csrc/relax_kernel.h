@@ -153,6 +153,15 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc(const RowStream &s
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(s.ptr), (short)0, ok ? row_bytes : 0,
                                              RSRC_WORD3);
 }
+// The same with a zero-sized descriptor also when `need` is false (a prefetch of a row the
+// tile does not use: the load returns zeros without touching memory).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stream_rsrc_if(const RowStream &s, int nrows, int row_bytes,
+                                                                bool need)
+{
+    const bool ok = need && (unsigned)s.row < (unsigned)nrows;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(s.ptr), (short)0, ok ? row_bytes : 0,
+                                             RSRC_WORD3);
+}
 template <int D> __device__ __forceinline__ void step_stream(RowStream &s, int row_bytes)
 {
     s.ptr += D > 0 ? (long long)row_bytes : -(long long)row_bytes;
@@ -711,6 +720,7 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
     const int rb = p.ld * ES, rbf = p.ld_f * ES;
     const A w = (A)p.w, lam = (A)p.lam;
     const int fc = VEC ? mc : mc - 1;
+    const int nsteps = y1 - y0 + 2 * K;  // steps whose input row the tile uses
     // Edge tiles (homogeneous Dirichlet) keep the ghost cells of every time level equal to
     // the odd reflection of their neighbours inside, as a refresh of the ghost layer
     // before each sweep would: after each level's row is formed, column 0 := -column 1 and
@@ -766,8 +776,11 @@ __device__ __forceinline__ void renamed_block(const KArgs &p, const Tile &tl, in
             for (int v = 0; v < V; ++v) lf[q][v] = lam * fv[v];
         }
         // rows x + D PR of phi and f (streams sin, sfr); level K stores row x - D K (sout)
-        pf[q % PR] = IO::load(stream_rsrc(sin, n + 2, rb), mc);
-        pff[q % PR] = IO::load(stream_rsrc(sfr, n, rbf), fc);
+        // (the last PR steps of the tile's rows need no further rows: their loads stay
+        // off memory -- the steps past them, up to a multiple of U, form no stored row)
+        const bool more = s + PR < nsteps;
+        pf[q % PR] = IO::load(stream_rsrc_if(sin, n + 2, rb, more), mc);
+        pff[q % PR] = IO::load(stream_rsrc_if(sfr, n, rbf, more), fc);
         step_stream<D>(sin, rb);
         step_stream<D>(sfr, rbf);
 #pragma unroll
