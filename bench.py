@@ -47,21 +47,21 @@ FP64_NOFMA_PEAK_TFLOPS = 256 * 64 * 2.4e9 / 1e12
 # HBM traffic of the FP64 fused relaxation at 4096^2, per launch: rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE (KiB per dispatch, averaged over the dispatches of a short bench run with
 # the given sweeps per launch and tile rows), scaled by what the same counters read for a
-# 1 GiB device-to-device copy (FETCH_SIZE 524302.625 KiB -> x 1048576 / 524302.625,
+# 1 GiB device-to-device copy (FETCH_SIZE 524302.65 KiB -> x 1048576 / 524302.65,
 # WRITE_SIZE 1048576 KiB -> x 1).  Valid only for the kernel sources they were taken on
 # (sha256 over TRAFFIC_SOURCES); otherwise the bench reports traffic as null.
 TRAFFIC_SOURCES = ("relax_kernel.h", "relax_f64.hip", "relax.hip", "px_internal.h")
-TRAFFIC_SHA256 = "a6a110ca8b6a5621cd8dc127eb15cc10144e51d722d80122f1c746eb3b5aa987"
-TRAFFIC_SCALE = (1048576.0 / 524302.625, 1.0)
+TRAFFIC_SHA256 = "7fd6930559948e47f25e77125dcc90d5c654d238abac978d37d49644d564df82"
+TRAFFIC_SCALE = (1048576.0 / 524302.65, 1.0)
 TRAFFIC_KIB = {  # (sweeps per launch, tile rows): (FETCH_SIZE, WRITE_SIZE) KiB per dispatch
-    (8, 29): (178710.23, 131264.06), (8, 38): (170733.41, 131264.07), (8, 44): (175402.73, 131264.06),
-    (8, 47): (163083.03, 131264.06), (1, 47): (147376.38, 131264.18),
+    (8, 29): (165920.44, 131264.06), (8, 38): (160775.76, 131264.06), (8, 44): (157887.19, 131264.06),
+    (8, 47): (156024.23, 131264.06), (1, 47): (147381.25, 131264.16),
 }
 # The same launches' memory-side request counters (TCC_EA0_RDREQ_DRAM_32B_sum and
 # TCC_EA0_WRREQ_WRITE_DRAM_32B_sum, 32-byte units, no scaling: the copy reads and writes
 # exactly its 1 GiB in them).  They count L2 misses sent to memory; no gfx950 counter
 # separates Infinity-Cache hits from HBM accesses.
-TRAFFIC_DRAM_32B = {(8, 47): (10298594, 4200450), (1, 47): (9430193, 4200453)}
+TRAFFIC_DRAM_32B = {(8, 47): (9838615, 4200450), (1, 47): (9430598, 4200454)}
 VARIANT_ROWS = (12, 16, 20, 29, 38, 47, 64, 96)  # tile heights tried for each fixed k in the variants
 METRIC = ("Gcell-updates/s & %HBM peak (fused relax); time-to-1e-10 residual learned/mixed vs plain")
 
