@@ -768,8 +768,8 @@ def main():
     ap.add_argument("--cpu-sweeps", type=int, default=SWEEPS)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the relaxation is sharded "
-              f"by box decomposition only in design, not in this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); sharding the relaxation over "
+              f"GPUs (box decomposition) is designed but not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch

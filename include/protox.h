@@ -67,7 +67,7 @@ extern "C" {
 typedef enum px_status {
     PX_OK = 0,
     PX_EINVAL = -1,        /* bad size, pointer, alignment, enum or value    */
-    PX_EUNSUPPORTED = -2,  /* valid request this build does not implement    */
+    PX_EUNSUPPORTED = -2,  /* valid request the library does not implement  */
     PX_EALIAS = -3,        /* an output overlaps an input it must not alias  */
     PX_EHIP = -4,          /* the HIP runtime reported an error              */
     PX_ENOTCONV = -5,      /* px_solve: max_sweeps reached before tolerance  */

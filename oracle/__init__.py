@@ -84,7 +84,7 @@ def lib() -> ctypes.CDLL:
 
 def default_threads() -> int:
     """Threads for the oracle's row loops: the CPUs this process may run on, at most 16
-    (a GPU machine's share of its host)."""
+    (one GPU's share of a multi-GPU host)."""
     try:
         cpus = len(os.sched_getaffinity(0))
     except (AttributeError, OSError):

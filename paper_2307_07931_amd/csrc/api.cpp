@@ -447,7 +447,7 @@ int noalloc_scratch(void **out)
     int dev = -1;
     PX_HIP(hipGetDevice(&dev), "hipGetDevice");
     if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
-        return fail(PX_EUNSUPPORTED, "device %d beyond the %d this build supports", dev, NOALLOC_MAX_DEVICES);
+        return fail(PX_EUNSUPPORTED, "device %d beyond the %d devices the library supports", dev, NOALLOC_MAX_DEVICES);
     std::lock_guard<std::mutex> lk(g_scratch_mu);
     if (!g_scratch_dev[dev]) {
         void *p = nullptr;
