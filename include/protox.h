@@ -109,8 +109,9 @@ int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
 
 /*
  * Autotuner: times the fused relaxation on the caller's buffers for every
- * sweeps-per-launch k in 1..8 and a list of tile heights (fastest of five
- * single launches each), re-times the four best as runs of 24 launches that
+ * sweeps-per-launch k in 1..8 and a list of tile heights (for k = 2, 5, 8
+ * those from 16 rows up rounded up to fill the unrolled loop's blocks of
+ * k + 1 steps; fastest of five single launches each), re-times the four best as runs of 24 launches that
  * each read the previous one's output (as a sweep loop runs them), gives the
  * two best of those a tile height for their launches that also take the
  * residual norms (fastest of three launches per height), times both as whole

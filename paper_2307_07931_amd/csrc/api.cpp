@@ -529,7 +529,6 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
     // Candidate tile heights: short bands give more waves, long bands less halo
     // recomputation; the best also depends on how the wave count divides the
     // resident wave slots, so the list is dense.
-    // (29, 38 and 47 make rows + 2k a multiple of k + 1 at k = 8, whole unrolled step blocks)
     static const int ROWS[] = {4, 6, 8, 12, 16, 20, 24, 28, 29, 32, 36, 38, 40, 44, 47, 48, 56, 64, 80, 96, 128};
     const double h = 1.0 / n, lambda = 0.25 * h * h * (2.0 / 3.0);
     hipEvent_t e0, e1;
@@ -543,7 +542,14 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
     Cand top[TOP] = {};
     int err = PX_OK;
     for (int k = 1; k <= 8 && !err; ++k) {
+        int last = -1;
         for (int rows : ROWS) {
+            // with k + 1 a multiple of 3 the unrolled loop runs blocks of k + 1 row steps: from
+            // 16 rows up, take the next height that fills its last block (rows + 2k a multiple
+            // of k + 1), whose partial block would otherwise compute rows it never stores
+            if ((k + 1) % 3 == 0 && rows >= 16) rows += ((k + 1) - (rows + 2 * k) % (k + 1)) % (k + 1);
+            if (rows == last) continue;
+            last = rows;
             if (rows > std::max(8, n + 2)) break;
             // one warm-up launch of k sweeps, then the fastest of five individually timed
             // launches (the minimum is robust against clock ramps and interference)
