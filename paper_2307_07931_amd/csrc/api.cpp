@@ -681,7 +681,15 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
             g4[c] = std::max(g4[c], g);
         }
     }
-    const int win = (g4[1] > g4[0]) ? 1 : 0;
+    // within 1.5% of each other the taller band wins at equal k: it recomputes fewer halo
+    // rows and reads less, and in long sweep loops (clocks settled, the memory system
+    // loaded) it has held up better than the timing of a few calls shows
+    int win = (g4[1] > g4[0]) ? 1 : 0;
+    {
+        const Cand &a = top[order[0]], &b = top[order[1]];
+        if (a.k == b.k && b.k != 0 && std::max(g4[0], g4[1]) <= 1.015 * std::min(g4[0], g4[1]))
+            win = (b.rows > a.rows) ? 1 : 0;
+    }
     const int bk = top[order[win]].k, br = top[order[win]].rows, brn = rn[win];
     const double bg = g4[win];
     (void)hipEventDestroy(e0);
