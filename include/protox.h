@@ -111,18 +111,18 @@ int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
  * Autotuner: times the fused relaxation on the caller's buffers for every
  * sweeps-per-launch k in 1..8 and a list of tile heights (for k = 2, 5, 8
  * those from 16 rows up rounded up to fill the unrolled loop's blocks of
- * k + 1 steps; fastest of five single launches each), re-times the four best as runs of 24 launches that
- * each read the previous one's output (as a sweep loop runs them), gives the
- * two best of those a tile height for their launches that also take the
- * residual norms (fastest of three launches per height), times both as whole
- * calls (24 launches, the last with norms) and remembers the faster (within
- * 1.5% at equal k: the taller band) in ctx for
- * this (dtype, n, ld).  Later
- * calls with tblock == 0 on such a grid use them (explicit tblock or
- * px_ctx_set_tile_rows override them).  phi_in is only read; phi_out is
- * overwritten with scratch iterates; f as in px_relax_fused.  Allocates the
- * context's ping-pong grid.  Waits on `stream`.  best_k, best_rows and gcells
- * (cell-updates per second / 1e9 of the winner) may be NULL.
+ * k + 1 steps; fastest of five single launches each), re-times the four best
+ * as runs of 24 launches that each read the previous one's output (as a sweep
+ * loop runs them), gives the two best of those a tile height for their
+ * launches that also take the residual norms (fastest of three launches per
+ * height), times both as whole calls (24 launches, the last with norms) and
+ * remembers the faster (within 1.5% at equal k: the taller band) in ctx for
+ * this (dtype, n, ld).  Later calls with tblock == 0 on such a grid use them
+ * (explicit tblock or px_ctx_set_tile_rows override them).  phi_in is only
+ * read; phi_out is overwritten with scratch iterates; f as in px_relax_fused.
+ * Allocates the context's ping-pong grid.  Waits on `stream`.  best_k,
+ * best_rows and gcells (cell-updates per second / 1e9 of the winner) may be
+ * NULL.
  */
 int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, const void *f,
                 int ld_f, int bc, px_ctx *ctx, void *stream, int *best_k, int *best_rows,
