@@ -115,8 +115,9 @@ int px_ctx_set_tile_rows(px_ctx *ctx, int rows);
  * as runs of 24 launches that each read the previous one's output (as a sweep
  * loop runs them), gives the two best of those a tile height for their
  * launches that also take the residual norms (fastest of three launches per
- * height), times both as whole calls (24 launches, the last with norms) and
- * remembers the faster (within 1.5% at equal k: the taller band) in ctx for
+ * height), times both as whole calls (24 launches, the last with norms;
+ * median of five) and remembers the faster (within 1.5% at equal k: the
+ * taller band) in ctx for
  * this (dtype, n, ld).  Later calls with tblock == 0 on such a grid use them
  * (explicit tblock or px_ctx_set_tile_rows override them).  phi_in is only
  * read; phi_out is overwritten with scratch iterates; f as in px_relax_fused.

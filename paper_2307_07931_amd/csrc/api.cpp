@@ -657,10 +657,13 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
         }
     }
     // final pass: each as a whole call makes it -- RUN launches from phi_in, each reading
-    // the previous output, the last one also taking the norms at its own height -- fastest
-    // of three
-    double g4[FIN] = {0.0, 0.0};
-    for (int round = 0; round < ROUNDS && !err; ++round) {
+    // the previous output, the last one also taking the norms at its own height -- the
+    // median of five alternating calls (a sweep loop runs at its typical, not its best,
+    // rate: the fastest of a few calls had favoured shorter bands that run slower on
+    // average)
+    constexpr int FROUNDS = 5;
+    double g5[FIN][FROUNDS] = {};
+    for (int round = 0; round < FROUNDS && !err; ++round) {
         for (int c = 0; c < FIN && !err; ++c) {
             const Cand &cd = top[order[c]];
             if (cd.k == 0) continue;
@@ -677,9 +680,13 @@ int px_autotune(const void *phi_in, void *phi_out, int n, int ld, int dtype, con
                 err = hip_fail(he, "autotune timing");
                 break;
             }
-            const double g = ms > 0.f ? RUN * cd.k * (double)n * n / (ms * 1e-3) / 1e9 : 0.0;
-            g4[c] = std::max(g4[c], g);
+            g5[c][round] = ms > 0.f ? RUN * cd.k * (double)n * n / (ms * 1e-3) / 1e9 : 0.0;
         }
+    }
+    double g4[FIN] = {0.0, 0.0};
+    for (int c = 0; c < FIN; ++c) {
+        std::sort(g5[c], g5[c] + FROUNDS);
+        g4[c] = g5[c][FROUNDS / 2];
     }
     // within 1.5% of each other the taller band wins at equal k: it recomputes fewer halo
     // rows and reads less, and in long sweep loops (clocks settled, the memory system
